@@ -1,0 +1,161 @@
+/*
+ * ozaki.h - C ABI of the MI355X (gfx950) Ozaki-I FP64 / complex-FP64 GEMM
+ * emulator (libozaki.so).
+ *
+ * The method is the Ozaki-I scheme as the paper describes it (Section 2.2,
+ * GEMM Emulation on Integer Matrix Multiplication Unit): exponent alignment,
+ * splitting of the FP64 inputs into low-precision slices, low-precision slice
+ * products, accumulation in higher precision. The paper applies it to the
+ * ZGEMM calls of the KKR/LSMS solver by intercepting standard BLAS calls
+ * (Section 3.1), so the interface is BLAS-shaped. The precise rules the paper
+ * leaves open are fixed as follows and are the same in every entry point:
+ *
+ *   exponents  e_i = frexp exponent of max_l max(|Re a_il|, |Im a_il|) over
+ *              row i of op(A); f_j likewise over column j of op(B). Zero
+ *              rows/columns take 0.
+ *   slices     x = a * 2^-e_i, then s signed 7-bit digits (truncation toward
+ *              zero): d_p = trunc(r * 2^7p), r -= d_p * 2^-7p. |d_p| <= 127.
+ *   products   S_t = sum_{p+q=t} SA_p SB_q for t = 2..s+1, exact integers
+ *              (INT8 x INT8 -> INT32 matrix cores, exact int64 carry when the
+ *              INT32 range would be exceeded). Complex data: four real products
+ *              per slice pair, Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br.
+ *   recombine  acc = 0; acc = RN(acc + S_t * 2^-7t) for t = 2..s+1; then
+ *              P_ij = acc * 2^(e_i + f_j).
+ *   alpha/beta C = alpha P + beta C with every product and sum rounded on its
+ *              own (complex: Re = (ar Pr - ai Pi) + (br Cr - bi Ci),
+ *              Im = (ar Pi + ai Pr) + (br Ci + bi Cr)). beta == 0: C is not
+ *              read. alpha == 0 or k == 0: C = beta C (untouched if beta == 1).
+ *   non-finite every C_ij whose row of op(A) or column of op(B) holds Inf or NaN
+ *              becomes NaN (a documented deviation from IEEE GEMM).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major with BLAS leading dimensions. trans is one of
+ *     'N', 'T', 'C' (case-insensitive); 'C' equals 'T' for real data.
+ *   - A, B, C (and every array passed to the debug hooks) are DEVICE pointers
+ *     owned by the caller; the library never frees them. Scratch memory comes
+ *     from the workspace given to ozaki_set_workspace, or else from a
+ *     grow-only device buffer the library allocates and frees in
+ *     ozaki_finalize.
+ *   - Work is enqueued on the stream given to ozaki_set_stream (default: the
+ *     null stream) and is asynchronous: the call returns before the result is
+ *     ready, the caller synchronises.
+ *   - Return value: 0 on success; -i when argument i (1-based, reference-BLAS
+ *     numbering) is invalid and nothing was launched; a positive OZAKI_ERR_*
+ *     code on a runtime failure.
+ *   - Calls are not thread safe: one host thread drives the library at a time.
+ */
+#ifndef OZAKI_H
+#define OZAKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Layout-compatible with C99 double _Complex and std::complex<double>. */
+typedef struct {
+  double re;
+  double im;
+} ozaki_z;
+
+#define OZAKI_S_MAX 12 /* slices accepted: 1..OZAKI_S_MAX */
+
+enum ozaki_status {
+  OZAKI_OK = 0,
+  OZAKI_ERR_HIP = 1,        /* a HIP runtime call or kernel launch failed */
+  OZAKI_ERR_ALLOC = 2,      /* device workspace could not be obtained */
+  OZAKI_ERR_WORKSPACE = 3,  /* the caller's workspace is too small */
+  OZAKI_ERR_NO_DEVICE = 4,  /* no usable gfx950 device */
+  OZAKI_ERR_INTERNAL = 5
+};
+
+/*
+ * C <- alpha op(A) op(B) + beta C, FP64, emulated with `slices` INT8 slices.
+ * op(A) is m x k, op(B) is k x n, C is m x n.
+ * Argument numbers for errors: transa 1, transb 2, m 3, n 4, k 5, lda 8,
+ * ldb 10, ldc 13, slices 14. lda >= max(1, rows of A as stored), likewise ldb,
+ * ldc >= max(1, m). m, n, k >= 0.
+ */
+int ozaki_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                double beta, double *C, int64_t ldc, int slices);
+
+/* Complex FP64 (interleaved re, im) version of ozaki_dgemm; same numbering. */
+int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb,
+                ozaki_z beta, ozaki_z *C, int64_t ldc, int slices);
+
+/*
+ * Native FP64 GEMM on the FP64 matrix cores (the comparator the paper uses as
+ * ground truth: native FP64 GEMM, Section 3.2). Same arguments and error
+ * numbering as ozaki_dgemm / ozaki_zgemm without `slices`. Ordinary FP64
+ * rounding (fused multiply-adds in an order fixed by the kernel); alpha/beta
+ * and quick returns as above; non-finite inputs propagate as IEEE arithmetic.
+ */
+int ozaki_native_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                       double alpha, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, double beta, double *C, int64_t ldc);
+int ozaki_native_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                       ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B,
+                       int64_t ldb, ozaki_z beta, ozaki_z *C, int64_t ldc);
+
+/* Stream for all later work (a hipStream_t; NULL = null stream). */
+int ozaki_set_stream(void *hip_stream);
+
+/*
+ * Caller-owned device workspace (NULL, 0 = use the library's own buffer).
+ * The library keeps the pointer until it is replaced; a call that needs more
+ * than `bytes` returns OZAKI_ERR_WORKSPACE. ozaki_workspace_bytes gives the
+ * size a call needs (kind 'd' or 'z').
+ */
+int ozaki_set_workspace(void *device_ptr, size_t bytes);
+size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int slices);
+
+/* Release the library's own device buffer (safe to call more than once). */
+int ozaki_finalize(void);
+
+/* Static text for a status code. */
+const char *ozaki_status_string(int status);
+
+/*
+ * Parity hooks. They run the same kernels as the GEMM entry points and copy
+ * intermediate results out in plain layouts; all output pointers are device
+ * pointers. kind is 'd' (X is double) or 'z' (X is ozaki_z).
+ *
+ * ozaki_debug_exponents: the exponent step on op(X) rows. side 'A': X is the
+ * A operand, rows are the `rows` rows of op(X) (an rows x L matrix);
+ * side 'B': X is the B operand, "rows" are the columns of op(X) (L x rows).
+ * Writes exps[r] (int32, e or f; 0 for a zero or flagged row) and flags[r]
+ * (uint8, 1 when the row holds Inf or NaN). Argument errors: -1 kind,
+ * -2 side, -3 trans, -4 rows, -5 L, -7 ldx, -8/-9 null outputs.
+ */
+int ozaki_debug_exponents(char kind, char side, char trans, int64_t rows, int64_t L,
+                          const void *X, int64_t ldx, int32_t *exps, uint8_t *flags);
+
+/*
+ * ozaki_debug_split: the digits d_1..d_s of op(X) rows (side 'A') or op(X)
+ * columns (side 'B'). Output layout: int8 digits[((p * rows + r) * L + l) * c + part]
+ * with p = 0..s-1, c = 1 (real) or 2 (complex, part 0 = Re, 1 = Im).
+ * Argument errors as ozaki_debug_exponents, -8 slices, -9 null output.
+ */
+int ozaki_debug_split(char kind, char side, char trans, int64_t rows, int64_t L,
+                      const void *X, int64_t ldx, int slices, int8_t *digits);
+
+/*
+ * ozaki_debug_diagonals: the exact diagonal sums S_t, t = 2..s+1, of
+ * op(A) op(B). Output layout: int64 S[(((t-2) * n + j) * m + i) * c + part],
+ * c = 1 (real) or 2 (complex, part 0 = Re, 1 = Im). Argument errors as the
+ * GEMM entry points (kind is argument 0: -100 when not 'd'/'z'), slices -14,
+ * null output -15.
+ */
+int ozaki_debug_diagonals(char kind, char transa, char transb, int64_t m, int64_t n,
+                          int64_t k, const void *A, int64_t lda, const void *B, int64_t ldb,
+                          int slices, int64_t *S);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZAKI_H */

@@ -1,0 +1,216 @@
+"""Python binding of libozaki, the MI355X (gfx950) Ozaki-I FP64/complex-FP64
+GEMM emulator.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libozaki.so (built in-tree by ``paper_2603_29975_amd/build.py``).
+There is no fallback: if the shared library is missing, importing a function
+that needs it raises ``OzakiUnavailable``.
+
+The functions named like the C ABI (``ozaki_dgemm`` ...) take column-major
+device buffers exactly as the C functions do: matrices are torch CUDA tensors
+(their ``data_ptr()`` is passed) or plain integer device addresses, and the
+return value is the C status code. They bind the current torch stream first.
+
+``matmul`` is a convenience on torch tensors in their usual row-major layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "OzakiError", "OzakiUnavailable", "ozaki_z", "library", "library_path",
+    "ozaki_dgemm", "ozaki_zgemm", "ozaki_native_dgemm", "ozaki_native_zgemm",
+    "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
+    "ozaki_finalize", "ozaki_status_string", "ozaki_debug_exponents",
+    "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libozaki.so")
+S_MAX = 12
+
+
+class OzakiUnavailable(ImportError):
+    pass
+
+
+class OzakiError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: status {status} ({ozaki_status_string(status)})")
+
+
+class ozaki_z(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+_c = ctypes
+_i64 = _c.c_int64
+_vp = _c.c_void_p
+_SIG = {
+    "ozaki_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp, _i64, _vp,
+                               _i64, _c.c_double, _vp, _i64, _c.c_int]),
+    "ozaki_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
+                               _i64, ozaki_z, _vp, _i64, _c.c_int]),
+    "ozaki_native_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp,
+                                      _i64, _vp, _i64, _c.c_double, _vp, _i64]),
+    "ozaki_native_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64,
+                                      _vp, _i64, ozaki_z, _vp, _i64]),
+    "ozaki_set_stream": (_c.c_int, [_vp]),
+    "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
+    "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
+    "ozaki_finalize": (_c.c_int, []),
+    "ozaki_status_string": (_c.c_char_p, [_c.c_int]),
+    "ozaki_debug_exponents": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _vp, _i64,
+                                         _vp, _vp]),
+    "ozaki_debug_split": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _vp, _i64,
+                                     _c.c_int, _vp]),
+    "ozaki_debug_diagonals": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _i64, _vp,
+                                         _i64, _vp, _i64, _c.c_int, _vp]),
+}
+
+_lib = None
+
+
+def library():
+    """The loaded libozaki.so (ctypes.CDLL). Raises OzakiUnavailable if it has
+    not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise OzakiUnavailable(
+                f"{library_path} is missing: build it with `python paper_2603_29975_amd/build.py` "
+                "(or __graft_entry__.build()); there is no fallback implementation")
+        lib = ctypes.CDLL(library_path)
+        for name, (res, args) in _SIG.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ch(c: str) -> bytes:
+    return c.encode("ascii") if isinstance(c, str) else bytes(c)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _z(v) -> ozaki_z:
+    v = complex(v)
+    return ozaki_z(v.real, v.imag)
+
+
+def _bind_stream():
+    import torch
+    if torch.cuda.is_available():
+        library().ozaki_set_stream(_c.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def ozaki_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices) -> int:
+    _bind_stream()
+    return library().ozaki_dgemm(_ch(transa), _ch(transb), m, n, k, float(alpha), _ptr(A), lda,
+                                 _ptr(B), ldb, float(beta), _ptr(C), ldc, int(slices))
+
+
+def ozaki_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, slices) -> int:
+    _bind_stream()
+    return library().ozaki_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
+                                 _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(slices))
+
+
+def ozaki_native_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    _bind_stream()
+    return library().ozaki_native_dgemm(_ch(transa), _ch(transb), m, n, k, float(alpha), _ptr(A),
+                                        lda, _ptr(B), ldb, float(beta), _ptr(C), ldc)
+
+
+def ozaki_native_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
+    _bind_stream()
+    return library().ozaki_native_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
+                                        _ptr(B), ldb, _z(beta), _ptr(C), ldc)
+
+
+def ozaki_set_stream(stream) -> int:
+    return library().ozaki_set_stream(_c.c_void_p(stream if isinstance(stream, int) or stream is None
+                                                  else stream.cuda_stream))
+
+
+def ozaki_set_workspace(ptr, nbytes: int) -> int:
+    return library().ozaki_set_workspace(_ptr(ptr), int(nbytes))
+
+
+def ozaki_workspace_bytes(kind, m, n, k, slices) -> int:
+    return library().ozaki_workspace_bytes(_ch(kind), m, n, k, int(slices))
+
+
+def ozaki_finalize() -> int:
+    return library().ozaki_finalize()
+
+
+def ozaki_status_string(status: int) -> str:
+    try:
+        return library().ozaki_status_string(int(status)).decode()
+    except OzakiUnavailable:
+        return "library not built"
+
+
+def ozaki_debug_exponents(kind, side, trans, rows, L, X, ldx, exps, flags) -> int:
+    _bind_stream()
+    return library().ozaki_debug_exponents(_ch(kind), _ch(side), _ch(trans), rows, L, _ptr(X), ldx,
+                                           _ptr(exps), _ptr(flags))
+
+
+def ozaki_debug_split(kind, side, trans, rows, L, X, ldx, slices, digits) -> int:
+    _bind_stream()
+    return library().ozaki_debug_split(_ch(kind), _ch(side), _ch(trans), rows, L, _ptr(X), ldx,
+                                       int(slices), _ptr(digits))
+
+
+def ozaki_debug_diagonals(kind, transa, transb, m, n, k, A, lda, B, ldb, slices, S) -> int:
+    _bind_stream()
+    return library().ozaki_debug_diagonals(_ch(kind), _ch(transa), _ch(transb), m, n, k, _ptr(A),
+                                           lda, _ptr(B), ldb, int(slices), _ptr(S))
+
+
+def matmul(A, B, slices: int = 7, alpha=1.0, beta=0.0, C=None, native: bool = False):
+    """C <- alpha A @ B + beta C for row-major torch CUDA tensors (float64 or
+    complex128, 2-D, unit stride along rows).
+
+    A row-major m x k tensor is the column-major k x m matrix A^T, so the call
+    computes C^T = B^T A^T in BLAS terms; the emulation is symmetric under this
+    transposition (exponents and slices are per row of A and per column of B
+    either way), so the result is the same as for the column-major problem.
+    """
+    import torch
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("shapes do not chain")
+    if A.dtype != B.dtype or A.dtype not in (torch.float64, torch.complex128):
+        raise TypeError("A and B must both be float64 or both complex128")
+    if A.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("rows must be unit stride")
+    m, k = A.shape
+    n = B.shape[1]
+    if C is None:
+        C = torch.empty((m, n), dtype=A.dtype, device=A.device)
+        beta = 0.0
+    elif C.shape != (m, n) or C.dtype != A.dtype or C.stride(1) != 1:
+        raise ValueError("bad C")
+    lda, ldb, ldc = max(1, A.stride(0)), max(1, B.stride(0)), max(1, C.stride(0))
+    cplx = A.dtype == torch.complex128
+    if native:
+        fn = ozaki_native_zgemm if cplx else ozaki_native_dgemm
+        rc = fn("N", "N", n, m, k, alpha, B, ldb, A, lda, beta, C, ldc)
+    else:
+        fn = ozaki_zgemm if cplx else ozaki_dgemm
+        rc = fn("N", "N", n, m, k, alpha, B, ldb, A, lda, beta, C, ldc, slices)
+    if rc != 0:
+        raise OzakiError(rc, fn.__name__)
+    return C

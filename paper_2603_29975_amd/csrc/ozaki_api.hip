@@ -1,0 +1,470 @@
+// Host runtime and C ABI of libozaki: argument checks, quick returns,
+// workspace, stream binding and the launch sequence of one emulated GEMM.
+//
+// One emulated call is four kernel kinds on the caller's stream:
+//   fill (zero the exponent codes) -> scan op(A) rows, op(B) columns ->
+//   split both operands into packed INT8 slices -> fused slice GEMM with FP64
+//   recombination and alpha/beta.
+// The interface mirrors a BLAS GEMM because the paper's solver reaches the
+// emulation through intercepted standard BLAS calls (Section 3.1).
+#include <algorithm>
+#include <cctype>
+#include <cstring>
+
+#include "../../include/ozaki.h"
+#include "ozaki_internal.hpp"
+
+namespace {
+
+using namespace oz;
+
+constexpr int kMaxDev = 16;
+
+struct DevInfo {
+  bool valid = false;
+  int num_cu = 0;
+};
+
+struct State {
+  hipStream_t stream = nullptr;
+  void *user_ws = nullptr;
+  size_t user_ws_bytes = 0;
+  void *own_ws[kMaxDev] = {};
+  size_t own_ws_bytes[kMaxDev] = {};
+  DevInfo dev[kMaxDev];
+};
+
+State g;
+
+char up(char c) { return (char)std::toupper((unsigned char)c); }
+bool trans_ok(char c) {
+  c = up(c);
+  return c == 'N' || c == 'T' || c == 'C';
+}
+
+int current_device(int *dev) {
+  if (hipGetDevice(dev) != hipSuccess) return OZAKI_ERR_NO_DEVICE;
+  if (*dev < 0 || *dev >= kMaxDev) return OZAKI_ERR_NO_DEVICE;
+  DevInfo &d = g.dev[*dev];
+  if (!d.valid) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, *dev) != hipSuccess || cu <= 0)
+      return OZAKI_ERR_NO_DEVICE;
+    d.num_cu = cu;
+    d.valid = true;
+  }
+  return OZAKI_OK;
+}
+
+// Workspace of at least `bytes`, from the caller's buffer or the library's own
+// grow-only buffer on the current device.
+int get_workspace(size_t bytes, void **out) {
+  if (bytes == 0) bytes = 256;
+  if (g.user_ws != nullptr) {
+    if (bytes > g.user_ws_bytes) return OZAKI_ERR_WORKSPACE;
+    *out = g.user_ws;
+    return OZAKI_OK;
+  }
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  if (g.own_ws_bytes[dev] < bytes) {
+    if (g.own_ws[dev] != nullptr) {
+      // hipFree waits for work still using the old buffer.
+      if (hipFree(g.own_ws[dev]) != hipSuccess) return OZAKI_ERR_HIP;
+      g.own_ws[dev] = nullptr;
+      g.own_ws_bytes[dev] = 0;
+    }
+    const size_t grow = std::max(bytes, (size_t)64 << 20);
+    void *p = nullptr;
+    if (hipMalloc(&p, grow) != hipSuccess) {
+      (void)hipGetLastError();
+      return OZAKI_ERR_ALLOC;
+    }
+    g.own_ws[dev] = p;
+    g.own_ws_bytes[dev] = grow;
+  }
+  *out = g.own_ws[dev];
+  return OZAKI_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Sizes of the packed operands of one emulated product.
+struct Plan {
+  int S;
+  bool cplx;
+  int64_t m, n, k;
+  int64_t kprime, kpad, nkb;
+  int64_t nprime;             // rows of B' (n or 2n)
+  int64_t nrbQ, nrbP;         // 32-row blocks of A' and B' (padded to 128 rows)
+  size_t off_codeA, off_codeB, off_SA, off_SB, off_flush, total;
+  int64_t kb_chunk;
+};
+
+Plan make_plan(bool cplx, int64_t m, int64_t n, int64_t k, int S, int num_cu) {
+  Plan p{};
+  p.S = S;
+  p.cplx = cplx;
+  p.m = m;
+  p.n = n;
+  p.k = k;
+  p.kprime = cplx ? 2 * k : k;
+  p.kpad = round_up(std::max<int64_t>(p.kprime, 1), kKPad);
+  p.nkb = p.kpad / 32;
+  p.nprime = cplx ? 2 * n : n;
+  p.nrbQ = round_up(std::max<int64_t>(m, 1), kRowPad) / 32;
+  p.nrbP = round_up(std::max<int64_t>(p.nprime, 1), kRowPad) / 32;
+  p.kb_chunk = kb_chunk_for(S);
+  size_t off = 0;
+  p.off_codeA = off;
+  off += align256(sizeof(int) * (size_t)std::max<int64_t>(m, 1));
+  p.off_codeB = off;
+  off += align256(sizeof(int) * (size_t)std::max<int64_t>(n, 1));
+  p.off_SA = off;
+  off += align256((size_t)S * p.nrbQ * 32 * p.kpad);
+  p.off_SB = off;
+  off += align256((size_t)S * p.nrbP * 32 * p.kpad);
+  p.off_flush = off;
+  if (p.nkb > p.kb_chunk) off += align256(gemm_flush_bytes(S, m, p.nprime, num_cu));
+  p.total = off;
+  return p;
+}
+
+View view_opA(const void *A, char trans, int64_t m, int64_t k, int64_t lda, bool cplx) {
+  View v;
+  v.base = A;
+  v.R = m;
+  v.L = k;
+  if (up(trans) == 'N') {
+    v.sr = 1;
+    v.sl = lda;
+  } else {
+    v.sr = lda;
+    v.sl = 1;
+  }
+  v.conj = cplx && up(trans) == 'C';
+  return v;
+}
+
+// Columns j of op(B) (k x n) as the rows of the view.
+View view_opB(const void *B, char trans, int64_t k, int64_t n, int64_t ldb, bool cplx) {
+  View v;
+  v.base = B;
+  v.R = n;
+  v.L = k;
+  if (up(trans) == 'N') {
+    v.sr = ldb;
+    v.sl = 1;
+  } else {
+    v.sr = 1;
+    v.sl = ldb;
+  }
+  v.conj = cplx && up(trans) == 'C';
+  return v;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? OZAKI_OK : OZAKI_ERR_HIP; }
+
+// BLAS argument checks; returns 0 or -(argument number).
+int check_gemm_args(char transa, char transb, int64_t m, int64_t n, int64_t k, int64_t lda,
+                    int64_t ldb, int64_t ldc) {
+  if (!trans_ok(transa)) return -1;
+  if (!trans_ok(transb)) return -2;
+  if (m < 0) return -3;
+  if (n < 0) return -4;
+  if (k < 0) return -5;
+  const int64_t nrowa = up(transa) == 'N' ? m : k;
+  const int64_t nrowb = up(transb) == 'N' ? k : n;
+  if (lda < std::max<int64_t>(1, nrowa)) return -8;
+  if (ldb < std::max<int64_t>(1, nrowb)) return -10;
+  if (ldc < std::max<int64_t>(1, m)) return -13;
+  return 0;
+}
+
+// Scan and split both operands into the workspace described by `p`.
+int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t st) {
+  int *codeA = reinterpret_cast<int *>(ws + p.off_codeA);
+  int *codeB = reinterpret_cast<int *>(ws + p.off_codeB);
+  int8_t *SA = reinterpret_cast<int8_t *>(ws + p.off_SA);
+  int8_t *SB = reinterpret_cast<int8_t *>(ws + p.off_SB);
+  int rc;
+  if ((rc = hip_rc(launch_fill_i32(codeA, p.m, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(codeB, p.n, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(va, p.cplx, codeA, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(vb, p.cplx, codeB, st)))) return rc;
+  if ((rc = hip_rc(launch_split(va, p.cplx, false, codeA, p.S, SA, p.nrbQ, p.nkb, st)))) return rc;
+  if ((rc = hip_rc(launch_split(vb, p.cplx, true, codeB, p.S, SB, p.nrbP, p.nkb, st)))) return rc;
+  return OZAKI_OK;
+}
+
+GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, double bi,
+                   bool beta_zero, void *C, int64_t ldc, int64_t *raw) {
+  GemmArgs a{};
+  a.SP = reinterpret_cast<const int8_t *>(ws + p.off_SB);
+  a.SQ = reinterpret_cast<const int8_t *>(ws + p.off_SA);
+  a.nrbP = p.nrbP;
+  a.nrbQ = p.nrbQ;
+  a.nkb = p.nkb;
+  a.m = p.m;
+  a.nprime = p.nprime;
+  a.codeA = reinterpret_cast<const int *>(ws + p.off_codeA);
+  a.codeB = reinterpret_cast<const int *>(ws + p.off_codeB);
+  a.ar = ar;
+  a.ai = ai;
+  a.br = br;
+  a.bi = bi;
+  a.beta_zero = beta_zero ? 1 : 0;
+  a.cplx = p.cplx ? 1 : 0;
+  a.C = C;
+  a.ldc = ldc;
+  a.flush_ws = reinterpret_cast<int64_t *>(ws + p.off_flush);
+  a.kb_chunk = p.kb_chunk;
+  a.raw = raw;
+  return a;
+}
+
+int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  double ar, double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                  double br, double bi, void *C, int64_t ldc, int slices) {
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
+  if (rc) return rc;
+  if (slices < 1 || slices > OZAKI_S_MAX) return -14;
+  if (m == 0 || n == 0) return OZAKI_OK;
+  if (C == nullptr) return -12;
+  const bool alpha_zero = ar == 0.0 && ai == 0.0;
+  const bool beta_zero = br == 0.0 && bi == 0.0;
+  const bool beta_one = br == 1.0 && bi == 0.0;
+  if (alpha_zero || k == 0) {
+    if (beta_one) return OZAKI_OK;
+    return hip_rc(launch_scale(cplx, m, n, br, bi, beta_zero, C, ldc, g.stream));
+  }
+  if (A == nullptr) return -7;
+  if (B == nullptr) return -9;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu);
+  void *wsv = nullptr;
+  if ((rc = get_workspace(p.total, &wsv))) return rc;
+  char *ws = static_cast<char *>(wsv);
+  const View va = view_opA(A, transa, m, k, lda, cplx);
+  const View vb = view_opB(B, transb, k, n, ldb, cplx);
+  if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
+  const GemmArgs ga = gemm_args(p, ws, ar, ai, br, bi, beta_zero, C, ldc, nullptr);
+  return hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+}
+
+int native_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k, double ar,
+                double ai, const void *A, int64_t lda, const void *B, int64_t ldb, double br,
+                double bi, void *C, int64_t ldc) {
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
+  if (rc) return rc;
+  if (m == 0 || n == 0) return OZAKI_OK;
+  if (C == nullptr) return -12;
+  const bool alpha_zero = ar == 0.0 && ai == 0.0;
+  const bool beta_zero = br == 0.0 && bi == 0.0;
+  const bool beta_one = br == 1.0 && bi == 0.0;
+  if (alpha_zero || k == 0) {
+    if (beta_one) return OZAKI_OK;
+    return hip_rc(launch_scale(cplx, m, n, br, bi, beta_zero, C, ldc, g.stream));
+  }
+  if (A == nullptr) return -7;
+  if (B == nullptr) return -9;
+  NativeArgs a{};
+  a.A = view_opA(A, transa, m, k, lda, cplx);
+  a.B = view_opB(B, transb, k, n, ldb, cplx);
+  a.m = m;
+  a.n = n;
+  a.k = k;
+  a.cplx = cplx ? 1 : 0;
+  a.ar = ar;
+  a.ai = ai;
+  a.br = br;
+  a.bi = bi;
+  a.beta_zero = beta_zero ? 1 : 0;
+  a.C = C;
+  a.ldc = ldc;
+  return hip_rc(launch_native(a, g.stream));
+}
+
+// View of op(X) for the debug hooks (see ozaki.h for `side`).
+int debug_view(char kind, char side, char trans, int64_t rows, int64_t L, const void *X,
+               int64_t ldx, View *v, bool *cplx) {
+  kind = up(kind);
+  side = up(side);
+  if (kind != 'D' && kind != 'Z') return -1;
+  if (side != 'A' && side != 'B') return -2;
+  if (!trans_ok(trans)) return -3;
+  if (rows < 0) return -4;
+  if (L < 0) return -5;
+  *cplx = kind == 'Z';
+  if (side == 'A') {
+    const int64_t need = up(trans) == 'N' ? rows : L;
+    if (ldx < std::max<int64_t>(1, need)) return -7;
+    *v = view_opA(X, trans, rows, L, ldx, *cplx);
+  } else {
+    const int64_t need = up(trans) == 'N' ? L : rows;
+    if (ldx < std::max<int64_t>(1, need)) return -7;
+    *v = view_opB(X, trans, L, rows, ldx, *cplx);
+  }
+  if (rows > 0 && L > 0 && X == nullptr) return -6;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ozaki_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                double *C, int64_t ldc, int slices) {
+  return emulated_gemm(false, transa, transb, m, n, k, alpha, 0.0, A, lda, B, ldb, beta, 0.0, C,
+                       ldc, slices);
+}
+
+int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, ozaki_z alpha,
+                const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb, ozaki_z beta,
+                ozaki_z *C, int64_t ldc, int slices) {
+  return emulated_gemm(true, transa, transb, m, n, k, alpha.re, alpha.im, A, lda, B, ldb, beta.re,
+                       beta.im, C, ldc, slices);
+}
+
+int ozaki_native_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                       double *C, int64_t ldc) {
+  return native_gemm(false, transa, transb, m, n, k, alpha, 0.0, A, lda, B, ldb, beta, 0.0, C, ldc);
+}
+
+int ozaki_native_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, ozaki_z alpha,
+                       const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb, ozaki_z beta,
+                       ozaki_z *C, int64_t ldc) {
+  return native_gemm(true, transa, transb, m, n, k, alpha.re, alpha.im, A, lda, B, ldb, beta.re,
+                     beta.im, C, ldc);
+}
+
+int ozaki_set_stream(void *hip_stream) {
+  g.stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return OZAKI_OK;
+}
+
+int ozaki_set_workspace(void *device_ptr, size_t bytes) {
+  if (device_ptr == nullptr) {
+    g.user_ws = nullptr;
+    g.user_ws_bytes = 0;
+    return OZAKI_OK;
+  }
+  if (bytes == 0) return -2;
+  g.user_ws = device_ptr;
+  g.user_ws_bytes = bytes;
+  return OZAKI_OK;
+}
+
+size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int slices) {
+  kind = up(kind);
+  if ((kind != 'D' && kind != 'Z') || m < 0 || n < 0 || k < 0 || slices < 1 ||
+      slices > OZAKI_S_MAX)
+    return 0;
+  int dev = 0;
+  int num_cu = 256;
+  if (current_device(&dev) == OZAKI_OK) num_cu = g.dev[dev].num_cu;
+  return make_plan(kind == 'Z', m, n, k, slices, num_cu).total;
+}
+
+int ozaki_finalize(void) {
+  int rc = OZAKI_OK;
+  for (int d = 0; d < kMaxDev; ++d) {
+    if (g.own_ws[d] != nullptr) {
+      int cur = 0;
+      if (hipGetDevice(&cur) != hipSuccess) rc = OZAKI_ERR_HIP;
+      if (hipSetDevice(d) != hipSuccess || hipFree(g.own_ws[d]) != hipSuccess) rc = OZAKI_ERR_HIP;
+      (void)hipSetDevice(cur);
+      g.own_ws[d] = nullptr;
+      g.own_ws_bytes[d] = 0;
+    }
+  }
+  return rc;
+}
+
+const char *ozaki_status_string(int status) {
+  if (status < 0) return "invalid argument";
+  switch (status) {
+    case OZAKI_OK: return "success";
+    case OZAKI_ERR_HIP: return "HIP runtime error";
+    case OZAKI_ERR_ALLOC: return "device workspace allocation failed";
+    case OZAKI_ERR_WORKSPACE: return "caller workspace too small";
+    case OZAKI_ERR_NO_DEVICE: return "no usable device";
+    case OZAKI_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+int ozaki_debug_exponents(char kind, char side, char trans, int64_t rows, int64_t L, const void *X,
+                          int64_t ldx, int32_t *exps, uint8_t *flags) {
+  View v;
+  bool cplx = false;
+  int rc = debug_view(kind, side, trans, rows, L, X, ldx, &v, &cplx);
+  if (rc) return rc;
+  if (rows == 0) return OZAKI_OK;
+  if (exps == nullptr) return -8;
+  if (flags == nullptr) return -9;
+  void *wsv = nullptr;
+  if ((rc = get_workspace(align256(sizeof(int) * rows), &wsv))) return rc;
+  int *code = static_cast<int *>(wsv);
+  if ((rc = hip_rc(launch_fill_i32(code, rows, 0, g.stream)))) return rc;
+  if ((rc = hip_rc(launch_scan(v, cplx, code, g.stream)))) return rc;
+  return hip_rc(launch_codes_to_exps(code, rows, exps, flags, g.stream));
+}
+
+int ozaki_debug_split(char kind, char side, char trans, int64_t rows, int64_t L, const void *X,
+                      int64_t ldx, int slices, int8_t *digits) {
+  View v;
+  bool cplx = false;
+  int rc = debug_view(kind, side, trans, rows, L, X, ldx, &v, &cplx);
+  if (rc) return rc;
+  if (slices < 1 || slices > OZAKI_S_MAX) return -8;
+  if (rows == 0 || L == 0) return OZAKI_OK;
+  if (digits == nullptr) return -9;
+  const bool side_b = up(side) == 'B';
+  const int64_t prows = (cplx && side_b) ? 2 * rows : rows;
+  const int64_t kpad = round_up(cplx ? 2 * L : L, kKPad);
+  const int64_t nrb = round_up(prows, kRowPad) / 32;
+  const size_t code_bytes = align256(sizeof(int) * rows);
+  const size_t total = code_bytes + align256((size_t)slices * nrb * 32 * kpad);
+  void *wsv = nullptr;
+  if ((rc = get_workspace(total, &wsv))) return rc;
+  int *code = static_cast<int *>(wsv);
+  int8_t *packed = static_cast<int8_t *>(wsv) + code_bytes;
+  if ((rc = hip_rc(launch_fill_i32(code, rows, 0, g.stream)))) return rc;
+  if ((rc = hip_rc(launch_scan(v, cplx, code, g.stream)))) return rc;
+  if ((rc = hip_rc(launch_split(v, cplx, side_b, code, slices, packed, nrb, kpad / 32, g.stream))))
+    return rc;
+  return hip_rc(launch_unpack(packed, cplx, side_b, rows, L, slices, nrb, kpad / 32, digits, g.stream));
+}
+
+int ozaki_debug_diagonals(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                          const void *A, int64_t lda, const void *B, int64_t ldb, int slices,
+                          int64_t *S) {
+  kind = up(kind);
+  if (kind != 'D' && kind != 'Z') return -100;
+  const bool cplx = kind == 'Z';
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, std::max<int64_t>(1, m));
+  if (rc) return rc;
+  if (slices < 1 || slices > OZAKI_S_MAX) return -14;
+  if (m == 0 || n == 0 || k == 0) return OZAKI_OK;
+  if (S == nullptr) return -15;
+  if (A == nullptr) return -7;
+  if (B == nullptr) return -9;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu);
+  void *wsv = nullptr;
+  if ((rc = get_workspace(p.total, &wsv))) return rc;
+  char *ws = static_cast<char *>(wsv);
+  const View va = view_opA(A, transa, m, k, lda, cplx);
+  const View vb = view_opB(B, transb, k, n, ldb, cplx);
+  if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
+  const GemmArgs ga = gemm_args(p, ws, 1.0, 0.0, 0.0, 0.0, true, nullptr, m, S);
+  return hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+}
+
+}  // extern "C"

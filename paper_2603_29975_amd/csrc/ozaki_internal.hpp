@@ -1,0 +1,67 @@
+// Internal launch interface between the host runtime (ozaki_api.hip) and the
+// kernel files of libozaki. Not part of the public C ABI.
+#pragma once
+
+#include "ozaki_common.hpp"
+
+namespace oz {
+
+// Exponent step: code[r] = max over row r of expo_code (code must hold zeros
+// on entry; launch_fill_i32 provides them).
+hipError_t launch_fill_i32(int *p, int64_t n, int value, hipStream_t st);
+hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st);
+
+// Slicing step: writes all nrb*32 x nkb*32 packed rows/entries of S slices.
+// side_b selects the B-operand construction for complex data (rows 2j and
+// 2j+1 hold (Re, -Im) and (Im, Re) of column j along the contraction).
+hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S,
+                        int8_t *out, int64_t nrb, int64_t nkb, hipStream_t st);
+
+// Debug helpers.
+hipError_t launch_unpack(const int8_t *packed, bool cplx, bool side_b, int64_t R, int64_t L,
+                         int S, int64_t nrb, int64_t nkb, int8_t *digits, hipStream_t st);
+hipError_t launch_codes_to_exps(const int *code, int64_t R, int32_t *exps, uint8_t *flags,
+                                hipStream_t st);
+
+// C <- beta C (beta_zero: C <- 0 without reading C).
+hipError_t launch_scale(bool cplx, int64_t m, int64_t n, double br, double bi, bool beta_zero,
+                        void *C, int64_t ldc, hipStream_t st);
+
+// Fused slice-pair GEMM + recombination.
+struct GemmArgs {
+  const int8_t *SP;  // packed B' (rows j' of the output's column side)
+  const int8_t *SQ;  // packed A' (rows i)
+  int64_t nrbP, nrbQ, nkb;
+  int64_t m, nprime;  // output rows i < m, output "rows" j' < nprime (n or 2n)
+  const int *codeA, *codeB;
+  double ar, ai, br, bi;
+  int beta_zero;
+  int cplx;
+  void *C;
+  int64_t ldc;
+  int64_t *flush_ws;   // int64 per-workgroup carry space (chunked K only)
+  int64_t kb_chunk;    // contraction blocks per exact INT32 chunk
+  int64_t *raw;        // raw diagonal output (debug) or nullptr
+};
+
+// Contraction blocks (of 32) that one INT32 accumulation may cover for S
+// slices: S * 32 * kb * 127^2 < 2^31.
+int64_t kb_chunk_for(int S);
+// Bytes of int64 carry space the GEMM needs when nkb > kb_chunk.
+size_t gemm_flush_bytes(int S, int64_t m, int64_t nprime, int num_cu);
+hipError_t launch_ozgemm(int S, const GemmArgs &a, int num_cu, hipStream_t st);
+
+// Native FP64 matrix-core GEMM.
+struct NativeArgs {
+  View A;  // op(A): rows i, contraction l
+  View B;  // op(B): rows j, contraction l
+  int64_t m, n, k;
+  int cplx;
+  double ar, ai, br, bi;
+  int beta_zero;
+  void *C;
+  int64_t ldc;
+};
+hipError_t launch_native(const NativeArgs &a, hipStream_t st);
+
+}  // namespace oz

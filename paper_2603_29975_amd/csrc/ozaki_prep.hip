@@ -1,0 +1,276 @@
+// Exponent scan, slicing and small helper kernels of libozaki (gfx950).
+//
+// Steps "exponent alignment" and "split into slices by significant bits" of
+// the Ozaki-I scheme (Section 2.2 of the paper). Both are HBM-bound: the scan
+// reads each operand once, the split reads it again and writes S (real) or
+// 2S (complex) bytes per element in the packed fragment layout.
+#include "ozaki_internal.hpp"
+
+namespace oz {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_fill_i32(int *p, int64_t n, int value) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+template <bool CPLX>
+__device__ __forceinline__ int elem_code(const void *base, int64_t off) {
+  if (CPLX) {
+    const double2 z = reinterpret_cast<const double2 *>(base)[off];
+    return max(expo_code(z.x), expo_code(z.y));
+  }
+  return expo_code(reinterpret_cast<const double *>(base)[off]);
+}
+
+// Rows are unit-stride in memory (sr == 1): 64 consecutive rows per block,
+// four threads per row walking the contraction index; each warp-wide load is
+// one contiguous run of 64 elements.
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_scan_rowsfast(View v, int64_t lchunk, int *code) {
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * 64 + (tid & 63);
+  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
+  const int64_t l1 = min(v.L, l0 + lchunk);
+  int c = 0;
+  if (r < v.R) {
+    for (int64_t l = l0 + (tid >> 6); l < l1; l += 4) c = max(c, elem_code<CPLX>(v.base, r + l * v.sl));
+  }
+  __shared__ int red[256];
+  red[tid] = c;
+  __syncthreads();
+  if (tid < 64) {
+    c = max(max(red[tid], red[tid + 64]), max(red[tid + 128], red[tid + 192]));
+    if (r < v.R && c > 0) atomicMax(code + r, c);
+  }
+}
+
+// Each row is unit-stride (sl == 1): one wave per row and contraction chunk,
+// lanes read consecutive elements, a wave max-reduction gives the row code.
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_scan_rowcontig(View v, int64_t lchunk, int *code) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= v.R) return;
+  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
+  const int64_t l1 = min(v.L, l0 + lchunk);
+  int c = 0;
+  for (int64_t l = l0 + lane; l < l1; l += 64) c = max(c, elem_code<CPLX>(v.base, r * v.sr + l));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off));
+  if (lane == 0 && c > 0) atomicMax(code + r, c);
+}
+
+// One thread per (packed row, 16 consecutive packed contraction entries):
+// reads the 16 source values (8 complex elements), splits each into S digits
+// and writes one 16-byte run per slice into the packed fragment layout.
+// Rows and entries beyond the operand are written as zero digits (padding).
+template <bool CPLX, bool SIDEB>
+__global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
+                                               int64_t nrb, int64_t nkb) {
+  const int tid = threadIdx.x;
+  const int64_t rp = (int64_t)blockIdx.x * 64 + (tid & 63);
+  const int64_t kp0 = ((int64_t)blockIdx.y * 4 + (tid >> 6)) * 16;
+  const int64_t Rrows = (CPLX && SIDEB) ? 2 * v.R : v.R;
+  const int64_t r = (CPLX && SIDEB) ? (rp >> 1) : rp;
+  const int cr = (CPLX && SIDEB) ? (int)(rp & 1) : 0;
+  const int c = (rp < Rrows) ? code[r] : 0;
+  const bool live = (rp < Rrows) && !code_bad(c);
+  const int e = code_exp(c);
+
+  Sig sg[16];
+  if (CPLX) {
+    const double2 *X = reinterpret_cast<const double2 *>(v.base);
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int64_t l = (kp0 >> 1) + x;
+      double re = 0.0, im = 0.0;
+      if (live && l < v.L) {
+        const double2 z = X[r * v.sr + l * v.sl];
+        re = z.x;
+        im = v.conj ? -z.y : z.y;
+      }
+      double v0, v1;
+      if (!SIDEB) {
+        v0 = re;
+        v1 = im;
+      } else if (cr == 0) {
+        v0 = re;
+        v1 = -im;
+      } else {
+        v0 = im;
+        v1 = re;
+      }
+      sg[2 * x] = decompose(v0, e);
+      sg[2 * x + 1] = decompose(v1, e);
+    }
+  } else {
+    const double *X = reinterpret_cast<const double *>(v.base);
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const int64_t l = kp0 + x;
+      double val = 0.0;
+      if (live && l < v.L) val = X[r * v.sr + l * v.sl];
+      sg[x] = decompose(val, e);
+    }
+  }
+
+  for (int p = 1; p <= S; ++p) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) word |= ((uint32_t)digit(sg[4 * q + b], p) & 0xffu) << (8 * b);
+      w[q] = word;
+    }
+    int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
+    *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <bool CPLX, bool SIDEB>
+__global__ void __launch_bounds__(256) k_unpack(const int8_t *packed, int64_t R, int64_t L, int S,
+                                                int64_t nrb, int64_t nkb, int8_t *digits) {
+  const int cc = CPLX ? 2 : 1;
+  const int64_t total = (int64_t)S * R * L * cc;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int part = (int)(idx % cc);
+  int64_t rest = idx / cc;
+  const int64_t l = rest % L;
+  rest /= L;
+  const int64_t r = rest % R;
+  const int p = (int)(rest / R);
+  int val;
+  if (!CPLX) {
+    val = packed[frag_offset(p, r, l, nrb, nkb)];
+  } else if (!SIDEB) {
+    val = packed[frag_offset(p, r, 2 * l + part, nrb, nkb)];
+  } else {
+    val = part == 0 ? packed[frag_offset(p, 2 * r, 2 * l, nrb, nkb)]
+                    : -packed[frag_offset(p, 2 * r, 2 * l + 1, nrb, nkb)];
+  }
+  digits[idx] = (int8_t)val;
+}
+
+__global__ void __launch_bounds__(256) k_codes(const int *code, int64_t R, int32_t *exps,
+                                               uint8_t *flags) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  const int c = code[r];
+  exps[r] = code_exp(c);
+  flags[r] = code_bad(c) ? 1 : 0;
+}
+
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_scale(int64_t m, int64_t n, double br, double bi,
+                                               int beta_zero, void *C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx % m, j = idx / m;
+  if (CPLX) {
+    double2 *c = reinterpret_cast<double2 *>(C) + i + j * ldc;
+    if (beta_zero) {
+      *c = make_double2(0.0, 0.0);
+    } else {
+      const double2 z = *c;
+      *c = make_double2(sub_rn(mul_rn(br, z.x), mul_rn(bi, z.y)), add_rn(mul_rn(br, z.y), mul_rn(bi, z.x)));
+    }
+  } else {
+    double *c = reinterpret_cast<double *>(C) + i + j * ldc;
+    *c = beta_zero ? 0.0 : mul_rn(br, *c);
+  }
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_fill_i32(int *p, int64_t n, int value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st) {
+  if (v.R <= 0 || v.L <= 0) return hipSuccess;
+  const int64_t target = 2048;
+  if (v.sr == 1 && !(v.sl == 1 && v.R < 64)) {
+    const int64_t rb = (v.R + 63) / 64;
+    int64_t ncol = std::max<int64_t>(1, std::min<int64_t>((v.L + 15) / 16, target / rb));
+    const int64_t lchunk = (v.L + ncol - 1) / ncol;
+    ncol = (v.L + lchunk - 1) / lchunk;
+    dim3 g((unsigned)rb, (unsigned)ncol);
+    if (cplx)
+      hipLaunchKernelGGL(k_scan_rowsfast<true>, g, dim3(256), 0, st, v, lchunk, code);
+    else
+      hipLaunchKernelGGL(k_scan_rowsfast<false>, g, dim3(256), 0, st, v, lchunk, code);
+  } else {
+    // sl == 1 (each row contiguous). A general-stride operand never reaches
+    // here: one of the two strides of a BLAS operand is always 1.
+    const int64_t rb = (v.R + 3) / 4;
+    int64_t ncol = std::max<int64_t>(1, std::min<int64_t>((v.L + 255) / 256, std::max<int64_t>(1, target / rb)));
+    const int64_t lchunk = (v.L + ncol - 1) / ncol;
+    ncol = (v.L + lchunk - 1) / lchunk;
+    dim3 g((unsigned)rb, (unsigned)ncol);
+    if (cplx)
+      hipLaunchKernelGGL(k_scan_rowcontig<true>, g, dim3(256), 0, st, v, lchunk, code);
+    else
+      hipLaunchKernelGGL(k_scan_rowcontig<false>, g, dim3(256), 0, st, v, lchunk, code);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S, int8_t *out,
+                        int64_t nrb, int64_t nkb, hipStream_t st) {
+  // nrb * 32 is a multiple of 64 (rows padded to 128) and nkb * 32 a multiple
+  // of 64 (contraction padded to 64): the grid covers the buffer exactly.
+  dim3 g((unsigned)(nrb * 32 / 64), (unsigned)(nkb * 32 / 64));
+  if (cplx) {
+    if (side_b)
+      hipLaunchKernelGGL((k_split<true, true>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
+    else
+      hipLaunchKernelGGL((k_split<true, false>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
+  } else {
+    hipLaunchKernelGGL((k_split<false, false>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const int8_t *packed, bool cplx, bool side_b, int64_t R, int64_t L, int S,
+                         int64_t nrb, int64_t nkb, int8_t *digits, hipStream_t st) {
+  const int64_t total = (int64_t)S * R * L * (cplx ? 2 : 1);
+  if (total <= 0) return hipSuccess;
+  dim3 g(grid1(total));
+  if (cplx) {
+    if (side_b)
+      hipLaunchKernelGGL((k_unpack<true, true>), g, dim3(256), 0, st, packed, R, L, S, nrb, nkb, digits);
+    else
+      hipLaunchKernelGGL((k_unpack<true, false>), g, dim3(256), 0, st, packed, R, L, S, nrb, nkb, digits);
+  } else {
+    hipLaunchKernelGGL((k_unpack<false, false>), g, dim3(256), 0, st, packed, R, L, S, nrb, nkb, digits);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_codes_to_exps(const int *code, int64_t R, int32_t *exps, uint8_t *flags,
+                                hipStream_t st) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codes, dim3(grid1(R)), dim3(256), 0, st, code, R, exps, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(bool cplx, int64_t m, int64_t n, double br, double bi, bool beta_zero,
+                        void *C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 g(grid1(m * n));
+  if (cplx)
+    hipLaunchKernelGGL(k_scale<true>, g, dim3(256), 0, st, m, n, br, bi, (int)beta_zero, C, ldc);
+  else
+    hipLaunchKernelGGL(k_scale<false>, g, dim3(256), 0, st, m, n, br, bi, (int)beta_zero, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace oz

@@ -1,0 +1,100 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments with reference-BLAS numbering before
+touching a GPU. No compute call is made here."""
+import os
+import re
+
+import pytest
+
+import paper_2603_29975_amd as oz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ozaki_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = oz.library()
+    names = _declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    for name in _declared_functions():
+        assert hasattr(oz, name), name
+
+
+@pytest.mark.parametrize("fn", ["ozaki_dgemm", "ozaki_zgemm"])
+def test_gemm_argument_errors(fn):
+    f = getattr(oz, fn)
+    ok = dict(transa="N", transb="N", m=4, n=5, k=6, alpha=1.0, A=0, lda=4, B=0, ldb=6, beta=0.0,
+              C=0, ldc=4, slices=7)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return f(a["transa"], a["transb"], a["m"], a["n"], a["k"], a["alpha"], a["A"], a["lda"],
+                 a["B"], a["ldb"], a["beta"], a["C"], a["ldc"], a["slices"])
+
+    assert call(transa="X") == -1
+    assert call(transb="Q") == -2
+    assert call(m=-1) == -3
+    assert call(n=-1) == -4
+    assert call(k=-1) == -5
+    assert call(lda=3) == -8
+    assert call(transa="T", lda=5) == -8          # rows of A as stored = k = 6
+    assert call(ldb=5) == -10
+    assert call(transb="C", ldb=4) == -10         # rows of B as stored = n = 5
+    assert call(ldc=3) == -13
+    assert call(slices=0) == -14
+    assert call(slices=13) == -14
+    assert call(C=0) == -12                       # null C with work to do
+    assert call(m=0) == 0 and call(n=0) == 0      # quick returns, nothing launched
+    assert call(A=0, C=1 << 40) == -7             # null A with alpha != 0 and k > 0
+    assert call(transa="n", transb="c", A=1 << 40, B=0, C=1 << 40, lda=4) == -9
+
+
+@pytest.mark.parametrize("fn", ["ozaki_native_dgemm", "ozaki_native_zgemm"])
+def test_native_argument_errors(fn):
+    f = getattr(oz, fn)
+    assert f("X", "N", 1, 1, 1, 1.0, 0, 1, 0, 1, 0.0, 0, 1) == -1
+    assert f("N", "N", 4, 1, 1, 1.0, 0, 3, 0, 1, 0.0, 0, 4) == -8
+    assert f("N", "N", 4, 2, 3, 1.0, 0, 4, 0, 2, 0.0, 0, 4) == -10
+    assert f("N", "N", 4, 2, 3, 1.0, 0, 4, 0, 3, 0.0, 0, 3) == -13
+    assert f("N", "N", 0, 2, 3, 1.0, 0, 4, 0, 3, 0.0, 0, 4) == 0
+
+
+def test_debug_hook_argument_errors():
+    assert oz.ozaki_debug_exponents("q", "A", "N", 1, 1, 0, 1, 0, 0) == -1
+    assert oz.ozaki_debug_exponents("d", "x", "N", 1, 1, 0, 1, 0, 0) == -2
+    assert oz.ozaki_debug_exponents("d", "A", "y", 1, 1, 0, 1, 0, 0) == -3
+    assert oz.ozaki_debug_exponents("d", "A", "N", -1, 1, 0, 1, 0, 0) == -4
+    assert oz.ozaki_debug_exponents("d", "A", "N", 3, 1, 0, 2, 0, 0) == -7
+    assert oz.ozaki_debug_split("z", "B", "N", 2, 3, 1 << 40, 3, 0, 0) == -8
+    assert oz.ozaki_debug_diagonals("x", "N", "N", 1, 1, 1, 0, 1, 0, 1, 3, 0) == -100
+    assert oz.ozaki_debug_diagonals("d", "N", "N", 1, 1, 1, 0, 1, 0, 1, 13, 0) == -14
+
+
+def test_status_strings_and_workspace_sizes():
+    assert oz.ozaki_status_string(0) == "success"
+    assert oz.ozaki_status_string(-4) == "invalid argument"
+    assert oz.ozaki_status_string(2) != oz.ozaki_status_string(1)
+    assert oz.ozaki_workspace_bytes("q", 1, 1, 1, 7) == 0
+    assert oz.ozaki_workspace_bytes("d", 1, 1, 1, 13) == 0
+    small = oz.ozaki_workspace_bytes("d", 256, 256, 256, 7)
+    big = oz.ozaki_workspace_bytes("z", 256, 256, 256, 7)
+    assert 0 < small < big
+    # packed slices dominate: s bytes per padded real entry of A' and B'
+    assert oz.ozaki_workspace_bytes("d", 256, 256, 256, 8) > small
+    assert small >= 7 * (256 * 256 + 256 * 256)
