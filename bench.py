@@ -1,0 +1,307 @@
+#!/usr/bin/env python3
+"""Benchmark of the INT8 Ozaki-I ZGEMM emulation on one MI355X.
+
+Workload (default): complex128 C = A B with M = N = K = 2048 shaped like the
+KKR multiple-scattering matrix (A = I - T G with 64 diagonal blocks of 32,
+seed 1002) and a complex Gaussian B, at s = 7 slices, the smallest slice count
+whose componentwise error reaches 1e-12 on this input. One step is one whole
+ozaki_zgemm call (exponent scan, slicing, fused slice GEMM + recombination) on
+operands already resident in HBM.
+
+Printed on stdout: one JSON line. `value` is effective FP64 TFLOP/s
+(8 m n k / wall time per call). Beside it: the hand-written native FP64-MFMA
+ZGEMM on the same buffers, per-phase times from HIP events recorded on the
+launch stream, the roofline of the dominant kernel (the fused INT8 slice GEMM)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "effective FP64 TFLOP/s, INT8-Ozaki ZGEMM vs native FP64 MFMA at ≤1e-12 rel err"
+INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 matrix peak
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix peak
+HBM_PEAK_GBS = 8000.0
+GEMM_SOURCE = os.path.join(ROOT, "paper_2603_29975_amd", "csrc", "ozaki_gemm.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ozgemm_kkr2048_s7_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import numpy as np
+    from workloads import kkr_operands, scaled_gaussian, uniform_binade
+    if name == "kkr2048":
+        A, B = kkr_operands(64, seed=1002)
+        return dict(name="kkr_zgemm_2048", kind="z", A=A, B=B, seed=1002,
+                    desc="A = I - T G (64 blocks of 32, |T| log-uniform in [1e-3,1], G decaying "
+                         "1/(1+d)), B complex Gaussian")
+    if name == "binade256":
+        A, B = uniform_binade(256, 256, 256, seed=1001)
+        return dict(name="binade_dgemm_256", kind="d", A=A, B=B, seed=1001,
+                    desc="u*2^e, u~U(-1,1), e~U-int[-4,4]")
+    if name == "ill4096":
+        A, B = scaled_gaussian(4096, 4096, 4096, seed=1004, rmax=30)
+        return dict(name="illcond_zgemm_4096", kind="z", A=A, B=B, seed=1004,
+                    desc="complex Gaussian, rows of A / columns of B scaled by 2^r, r~U-int[-30,30]")
+    if name == "ill16384":
+        A, B = scaled_gaussian(16384, 16384, 16384, seed=1004, rmax=30)
+        return dict(name="illcond_zgemm_16384", kind="z", A=A, B=B, seed=1004,
+                    desc="complex Gaussian, rows of A / columns of B scaled by 2^r, r~U-int[-30,30]")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(per_launch_ops: float):
+    """HBM bytes per launch of the fused GEMM kernel from the committed counter
+    summary, or None when it is missing or was taken on another kernel source."""
+    try:
+        vals = {}
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCE):
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--workload", default="kkr2048",
+                    choices=["kkr2048", "binade256", "ill4096", "ill16384"])
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (timing and accuracy check)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the emulator runs on a single MI355X and has no "
+              "multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2603_29975_amd as oz
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    oz.library()   # fails loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = workload(args.workload)
+    A, B = wl["A"], wl["B"]
+    kind = wl["kind"]
+    m, k = A.shape
+    n = B.shape[1]
+    s = args.slices
+    cplx = kind == "z"
+    tdt = torch.complex128 if cplx else torch.float64
+    log(f"workload {wl['name']} m={m} n={n} k={k} s={s}")
+
+    # Column-major device operands: the row-major tensor of X^T is X column-major.
+    Ad = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev)
+    Bd = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    Cd = torch.zeros((n, m), dtype=tdt, device=dev)
+    Cn = torch.zeros((n, m), dtype=tdt, device=dev)
+    gemm = oz.ozaki_zgemm if cplx else oz.ozaki_dgemm
+    native = oz.ozaki_native_zgemm if cplx else oz.ozaki_native_dgemm
+
+    def run_ozaki(slices=s, out=Cd):
+        rc = gemm("N", "N", m, n, k, 1.0, Ad, m, Bd, k, 0.0, out, m, slices)
+        if rc != 0:
+            raise RuntimeError(f"{gemm.__name__}: {oz.ozaki_status_string(rc)}")
+
+    def run_native():
+        rc = native("N", "N", m, n, k, 1.0, Ad, m, Bd, k, 0.0, Cn, m)
+        if rc != 0:
+            raise RuntimeError(f"{native.__name__}: {oz.ozaki_status_string(rc)}")
+
+    flops = (8.0 if cplx else 2.0) * m * n * k          # effective FP64 flops per call
+    pairs = s * (s + 1) // 2
+    int8_ops = pairs * flops                             # INT8 ops of the slice GEMM per call
+
+    # ---------------------------------------------------------------- emulation
+    for _ in range(args.warmup):
+        run_ozaki()
+    torch.cuda.synchronize()
+    oz.ozaki_timing_enable(True)
+    oz.ozaki_timing_read()                               # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_ozaki()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, phase_ms, calls = oz.ozaki_timing_read()
+    oz.ozaki_timing_enable(False)
+    if rc != 0 or calls != args.steps:
+        raise RuntimeError(f"phase timing failed: rc={rc} calls={calls}")
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    phases = {p: v / args.steps for p, v in phase_ms.items()}
+    log(f"ozaki: {ms_per_step:.3f} ms/call  {value:.2f} eff TFLOP/s  phases {phases}")
+
+    gemm_ms = phases["gemm"]
+    achieved = int8_ops / (gemm_ms * 1e-3) / 1e12
+    traffic = read_traffic(int8_ops)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
+                "traffic": traffic,
+                "kernel": "k_ozgemm (fused INT8 slice-pair GEMM + FP64 recombination)",
+                "ops_per_launch": int8_ops, "avg_launch_ms": round(gemm_ms, 4),
+                "note": "INT8 MFMA work counted as 2 ops per multiply-add against the "
+                        "5000 TOP/s dense INT8 peak"}
+
+    # ---------------------------------------------------------------- native
+    native_rec = None
+    if not args.no_native:
+        for _ in range(args.warmup):
+            run_native()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run_native()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nms = (t1 - t0) * 1e3 / args.steps
+        ntf = flops / (nms * 1e-3) / 1e12
+        native_rec = {"kernel": "k_native (FP64 MFMA 16x16x4)", "ms_per_call": round(nms, 4),
+                      "tflops": round(ntf, 2), "frac_of_fp64_peak": round(ntf / FP64_PEAK_TFLOPS, 4)}
+        log(f"native: {nms:.3f} ms/call  {ntf:.2f} TFLOP/s")
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read, {nb} bytes written (torch.neg)")
+
+    # ---------------------------------------------------------------- CPU oracle leg
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        cpu, accuracy = cpu_leg(wl, s, Cd, m, n, k, run_ozaki, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "m": m, "n": n, "k": k,
+                   "operands": "complex128" if cplx else "float64", "slices": s,
+                   "pairs": pairs, "seed": wl["seed"], "inputs": wl["desc"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "native_fp64": native_rec,
+        "speedup_vs_native": (round(native_rec["ms_per_call"] / ms_per_step, 3)
+                              if native_rec else None),
+        "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+        "accuracy": accuracy,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
+    """The oracle timed on a bounded sample (rows 0..ms-1 of op(A) against the
+    whole op(B)), plus the accuracy check of the GPU result on sampled entries
+    against the oracle's double-double reference."""
+    import numpy as np
+    import torch
+    from oracle import dd, metrics, ozaki
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                       if p.get("user_api") == "blas"] or [1])
+    except Exception:   # noqa: BLE001
+        threads = os.cpu_count() or 1
+    A, B = wl["A"], wl["B"]
+    torch.cuda.synchronize()
+    C = Cd.cpu().numpy().T
+
+    # accuracy on 1024 sampled entries, at s and at s - 1
+    rng = np.random.default_rng(2024)
+    ri = rng.integers(0, m, 1024)
+    cj = rng.integers(0, n, 1024)
+    hi, lo = dd.dd_entries("N", "N", A, B, ri, cj)
+    den = metrics.denom_entries("N", "N", A, B, ri, cj)
+    err_s = metrics.err_comp(C[ri, cj], hi, lo, den)
+    err_prev = None
+    if s > 1:
+        Cprev = torch.zeros_like(Cd)
+        run_ozaki(s - 1, Cprev)
+        torch.cuda.synchronize()
+        Cp = Cprev.cpu().numpy().T
+        err_prev = metrics.err_comp(Cp[ri, cj], hi, lo, den)
+    # bit-exact spot check against the oracle model on 8 rows x 8 columns
+    rs = np.sort(rng.choice(m, 8, replace=False))
+    cs = np.sort(rng.choice(n, 8, replace=False))
+    ref = ozaki.ozaki_gemm("N", "N", A[rs], B[:, cs], s)
+    exact = bool(np.array_equal(C[np.ix_(rs, cs)].view(np.uint64), ref.view(np.uint64)))
+    accuracy = {"err_comp_sampled": err_s, "err_comp_sampled_s_minus_1": err_prev,
+                "entries": 1024, "reference": "double-double (oracle)",
+                "target": 1e-12, "meets_target": bool(err_s <= 1e-12),
+                "oracle_bit_exact_8x8": exact}
+    log(f"accuracy: err_comp(s={s}) {err_s:.3e}  (s-1) {err_prev}  bit-exact 8x8 {exact}")
+
+    # oracle timing on a bounded sample
+    def timed(rows):
+        t0 = time.perf_counter()
+        ozaki.ozaki_gemm("N", "N", A[:rows], B, s)
+        return time.perf_counter() - t0
+
+    # cost model t(rows) = fixed + per_row * rows from two small probes
+    r1, r2 = min(m, 4), min(m, 16)
+    t1, t2 = timed(r1), timed(r2)
+    per_row = max((t2 - t1) / max(r2 - r1, 1), 1e-6)
+    fixed = max(t1 - per_row * r1, 0.0)
+    rows = int(max(r2, min(m, (target_s - fixed) / per_row)))
+    t = timed(rows)
+    flops = (8.0 if np.iscomplexobj(A) else 2.0) * rows * n * k
+    cpu = {"value": round(flops / t / 1e12, 6), "unit": "TFLOP/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"oracle Ozaki model (numpy + host BLAS on integer slices) for rows 0..{rows - 1} "
+                     f"of op(A) against all of op(B): {rows}x{n}x{k}, s={s}, {t:.2f} s",
+           "host_cpus": os.cpu_count()}
+    log(f"cpu oracle: {cpu}")
+    return cpu, accuracy
+
+
+if __name__ == "__main__":
+    main()

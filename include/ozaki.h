@@ -113,6 +113,24 @@ int ozaki_set_stream(void *hip_stream);
 int ozaki_set_workspace(void *device_ptr, size_t bytes);
 size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int slices);
 
+/*
+ * Phase timing for measurement. While enabled, every emulated GEMM records a
+ * pair of HIP events around each of its phases on the call's stream:
+ *   OZAKI_PHASE_SCAN  exponent scan of op(A) rows and op(B) columns
+ *   OZAKI_PHASE_SPLIT slicing of both operands into packed INT8 slices
+ *   OZAKI_PHASE_GEMM  fused slice-pair INT8 GEMM + FP64 recombination
+ * ozaki_timing_read waits for the recorded events, writes the summed
+ * milliseconds per phase into ms[0..OZAKI_PHASES-1] (host array) and the
+ * number of timed calls into *calls (may be NULL), then clears the record.
+ * Recording adds one event pair per phase and call; leave it off otherwise.
+ */
+#define OZAKI_PHASES 3
+#define OZAKI_PHASE_SCAN 0
+#define OZAKI_PHASE_SPLIT 1
+#define OZAKI_PHASE_GEMM 2
+int ozaki_timing_enable(int on);
+int ozaki_timing_read(double *ms, int64_t *calls);
+
 /* Release the library's own device buffer (safe to call more than once). */
 int ozaki_finalize(void);
 

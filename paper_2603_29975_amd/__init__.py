@@ -22,7 +22,7 @@ __all__ = [
     "OzakiError", "OzakiUnavailable", "ozaki_z", "library", "library_path",
     "ozaki_dgemm", "ozaki_zgemm", "ozaki_native_dgemm", "ozaki_native_zgemm",
     "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
-    "ozaki_finalize", "ozaki_status_string", "ozaki_debug_exponents",
+    "ozaki_finalize", "ozaki_status_string", "ozaki_timing_enable", "ozaki_timing_read", "ozaki_debug_exponents",
     "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX",
 ]
 
@@ -61,6 +61,8 @@ _SIG = {
     "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
     "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
     "ozaki_finalize": (_c.c_int, []),
+    "ozaki_timing_enable": (_c.c_int, [_c.c_int]),
+    "ozaki_timing_read": (_c.c_int, [_vp, _vp]),
     "ozaki_status_string": (_c.c_char_p, [_c.c_int]),
     "ozaki_debug_exponents": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _vp, _i64,
                                          _vp, _vp]),
@@ -149,6 +151,21 @@ def ozaki_set_workspace(ptr, nbytes: int) -> int:
 
 def ozaki_workspace_bytes(kind, m, n, k, slices) -> int:
     return library().ozaki_workspace_bytes(_ch(kind), m, n, k, int(slices))
+
+
+PHASES = ("scan", "split", "gemm")
+
+
+def ozaki_timing_enable(on: bool) -> int:
+    return library().ozaki_timing_enable(1 if on else 0)
+
+
+def ozaki_timing_read():
+    """(status, {phase: total ms}, calls) since the last read."""
+    ms = (_c.c_double * len(PHASES))()
+    calls = _c.c_int64(0)
+    rc = library().ozaki_timing_read(_c.cast(ms, _c.c_void_p), _c.cast(_c.pointer(calls), _c.c_void_p))
+    return rc, {p: ms[i] for i, p in enumerate(PHASES)}, calls.value
 
 
 def ozaki_finalize() -> int:

@@ -2,15 +2,19 @@
 //
 // The comparator of the emulation: the paper's ground truth and speed
 // baseline is native FP64 GEMM (Section 3.2). Same output orientation as the
-// emulated kernel: MFMA rows are the output column side j' (j' = 2j + c for
-// complex data), MFMA columns are output rows i, so stores are contiguous in
-// column-major C.
+// emulated kernel: MFMA rows are the output column side j' (the real- and
+// imaginary-part rows of each column for complex data), MFMA columns are
+// output rows i, so stores are contiguous in column-major C.
 //
 // Complex data is computed as one real GEMM over a contraction of length 2k:
-// A'(i, 2l) = Re a_il, A'(i, 2l+1) = Im a_il; B' rows 2j and 2j+1 hold
-// (Re b_lj, -Im b_lj) and (Im b_lj, Re b_lj) at contraction positions
-// (2l, 2l+1). Then sum_k' B'(2j, k') A'(i, k') = Re (AB)_ij and row 2j+1 gives
+// A'(i, 2l) = Re a_il, A'(i, 2l+1) = Im a_il; for column j of op(B) one B' row
+// holds (Re b_lj, -Im b_lj) and another (Im b_lj, Re b_lj) at contraction
+// positions (2l, 2l+1). The first row times A' gives Re (AB)_ij, the second
 // Im (AB)_ij: four real products per complex product, as a plain ZGEMM does.
+// Within each 16-row MFMA block, rows 0..7 are the real-part rows of 8
+// consecutive columns j and rows 8..15 their imaginary-part rows. The FP64
+// MFMA leaves D[l/16 + 4r][l%16] in lane l, register r, so registers r and
+// r + 2 of a lane hold Re and Im of the same C entry.
 //
 // Tiles: 256 threads = 2 x 2 waves, wave tile 64 (j') x 64 (i) = 4 x 4 MFMA
 // blocks of 16 x 16, contraction 16 per stage, LDS double buffered with a
@@ -113,10 +117,12 @@ __global__ void __launch_bounds__(NTH) k_native(NativeArgs a) {
       const int ll = p_rows_fast ? e / PR : e % PL;
       if constexpr (CPLX) {
         const double2 z = pbuf[x];
-        P[(2 * ll) * LDJ + 2 * rl] = z.x;
-        P[(2 * ll + 1) * LDJ + 2 * rl] = -z.y;
-        P[(2 * ll) * LDJ + 2 * rl + 1] = z.y;
-        P[(2 * ll + 1) * LDJ + 2 * rl + 1] = z.x;
+        const int rre = 16 * (rl >> 3) + (rl & 7);  // real-part row of column rl
+        const int rim = rre + 8;                    // imaginary-part row
+        P[(2 * ll) * LDJ + rre] = z.x;
+        P[(2 * ll + 1) * LDJ + rre] = -z.y;
+        P[(2 * ll) * LDJ + rim] = z.y;
+        P[(2 * ll + 1) * LDJ + rim] = z.x;
       } else {
         P[ll * LDJ + rl] = pbuf[x];
       }
@@ -170,23 +176,23 @@ __global__ void __launch_bounds__(NTH) k_native(NativeArgs a) {
     __syncthreads();
   }
 
-  // Epilogue: lane holds rows j' = base + 4*(lane/16) + r (r = 0..3) of column
-  // i = base + lane % 16 of each 16 x 16 block.
+  // Epilogue: lane l holds rows l/16 + 4r (r = 0..3) of column l%16 of each
+  // 16 x 16 block.
 #pragma unroll
   for (int y = 0; y < 4; ++y) {
     const int64_t i = i0 + wi * 64 + y * 16 + col;
     if (i >= a.m) continue;
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      const int64_t jb = j0 + wj * 64 + x * 16 + 4 * krow;
+      const int64_t rb = j0 + wj * 64 + x * 16;  // first j' of the block
       if constexpr (CPLX) {
         double2 *C = reinterpret_cast<double2 *>(a.C);
 #pragma unroll
-        for (int r = 0; r < 4; r += 2) {
-          const int64_t j = (jb + r) >> 1;
+        for (int r = 0; r < 2; ++r) {
+          const int64_t j = rb / 2 + krow + 4 * r;
           if (j >= a.n) continue;
           double2 *cp = C + i + j * a.ldc;
-          const double pr = acc[x][y][r], pi = acc[x][y][r + 1];
+          const double pr = acc[x][y][r], pi = acc[x][y][r + 2];
           double re = sub_rn(mul_rn(a.ar, pr), mul_rn(a.ai, pi));
           double im = add_rn(mul_rn(a.ar, pi), mul_rn(a.ai, pr));
           if (!a.beta_zero) {
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(NTH) k_native(NativeArgs a) {
         double *C = reinterpret_cast<double *>(a.C);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t j = jb + r;
+          const int64_t j = rb + krow + 4 * r;
           if (j >= nprime) continue;
           double *cp = C + i + j * a.ldc;
           double out = mul_rn(a.ar, acc[x][y][r]);

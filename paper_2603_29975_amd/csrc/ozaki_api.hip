@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cctype>
 #include <cstring>
+#include <vector>
 
 #include "../../include/ozaki.h"
 #include "ozaki_internal.hpp"
@@ -35,6 +36,45 @@ struct State {
 };
 
 State g;
+
+// ---------------------------------------------------------------- timing
+struct Mark {
+  int phase;
+  hipEvent_t start, stop;
+};
+struct Timing {
+  bool on = false;
+  int64_t calls = 0;
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+Timing g_tm;
+
+hipEvent_t take_event() {
+  if (!g_tm.pool.empty()) {
+    hipEvent_t e = g_tm.pool.back();
+    g_tm.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start of `phase` on the stream; returns the mark index or -1.
+int phase_begin(int phase, hipStream_t st) {
+  if (!g_tm.on) return -1;
+  Mark mk{phase, take_event(), take_event()};
+  if (mk.start == nullptr || mk.stop == nullptr) return -1;
+  if (hipEventRecord(mk.start, st) != hipSuccess) return -1;
+  g_tm.marks.push_back(mk);
+  return (int)g_tm.marks.size() - 1;
+}
+
+void phase_end(int idx, hipStream_t st) {
+  if (idx < 0) return;
+  (void)hipEventRecord(g_tm.marks[idx].stop, st);
+}
 
 char up(char c) { return (char)std::toupper((unsigned char)c); }
 bool trans_ok(char c) {
@@ -189,12 +229,16 @@ int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t
   int8_t *SA = reinterpret_cast<int8_t *>(ws + p.off_SA);
   int8_t *SB = reinterpret_cast<int8_t *>(ws + p.off_SB);
   int rc;
+  int mk = phase_begin(OZAKI_PHASE_SCAN, st);
   if ((rc = hip_rc(launch_fill_i32(codeA, p.m, 0, st)))) return rc;
   if ((rc = hip_rc(launch_fill_i32(codeB, p.n, 0, st)))) return rc;
   if ((rc = hip_rc(launch_scan(va, p.cplx, codeA, st)))) return rc;
   if ((rc = hip_rc(launch_scan(vb, p.cplx, codeB, st)))) return rc;
+  phase_end(mk, st);
+  mk = phase_begin(OZAKI_PHASE_SPLIT, st);
   if ((rc = hip_rc(launch_split(va, p.cplx, false, codeA, p.S, SA, p.nrbQ, p.nkb, st)))) return rc;
   if ((rc = hip_rc(launch_split(vb, p.cplx, true, codeB, p.S, SB, p.nrbP, p.nkb, st)))) return rc;
+  phase_end(mk, st);
   return OZAKI_OK;
 }
 
@@ -251,7 +295,11 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
   if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
   const GemmArgs ga = gemm_args(p, ws, ar, ai, br, bi, beta_zero, C, ldc, nullptr);
-  return hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+  const int mk = phase_begin(OZAKI_PHASE_GEMM, g.stream);
+  rc = hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+  phase_end(mk, g.stream);
+  if (g_tm.on) ++g_tm.calls;
+  return rc;
 }
 
 int native_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k, double ar,
@@ -368,6 +416,31 @@ size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int sli
   int num_cu = 256;
   if (current_device(&dev) == OZAKI_OK) num_cu = g.dev[dev].num_cu;
   return make_plan(kind == 'Z', m, n, k, slices, num_cu).total;
+}
+
+int ozaki_timing_enable(int on) {
+  g_tm.on = on != 0;
+  return OZAKI_OK;
+}
+
+int ozaki_timing_read(double *ms, int64_t *calls) {
+  if (ms == nullptr) return -1;
+  for (int p = 0; p < OZAKI_PHASES; ++p) ms[p] = 0.0;
+  int rc = OZAKI_OK;
+  for (Mark &mk : g_tm.marks) {
+    float t = 0.0f;
+    if (hipEventSynchronize(mk.stop) != hipSuccess ||
+        hipEventElapsedTime(&t, mk.start, mk.stop) != hipSuccess)
+      rc = OZAKI_ERR_HIP;
+    else if (mk.phase >= 0 && mk.phase < OZAKI_PHASES)
+      ms[mk.phase] += (double)t;
+    g_tm.pool.push_back(mk.start);
+    g_tm.pool.push_back(mk.stop);
+  }
+  g_tm.marks.clear();
+  if (calls != nullptr) *calls = g_tm.calls;
+  g_tm.calls = 0;
+  return rc;
 }
 
 int ozaki_finalize(void) {
