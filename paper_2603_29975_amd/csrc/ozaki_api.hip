@@ -9,6 +9,7 @@
 // emulation through intercepted standard BLAS calls (Section 3.1).
 #include <algorithm>
 #include <cctype>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -166,7 +167,7 @@ Plan make_plan(bool cplx, int64_t m, int64_t n, int64_t k, int S, int num_cu) {
   p.off_SB = off;
   off += align256((size_t)S * p.nrbP * 32 * p.kpad);
   p.off_flush = off;
-  if (p.nkb > p.kb_chunk) off += align256(gemm_flush_bytes(S, m, p.nprime, num_cu));
+  if (p.nkb > p.kb_chunk) off += align256(gemm_flush_bytes(S, 0, num_cu));
   p.total = off;
   return p;
 }
@@ -205,6 +206,22 @@ View view_opB(const void *B, char trans, int64_t k, int64_t n, int64_t ldb, bool
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? OZAKI_OK : OZAKI_ERR_HIP; }
+
+// Tile configuration of the fused GEMM: OZAKI_GEMM_CONFIG overrides the
+// default (0) for experiments and tuning.
+int gemm_config(int S, int64_t m, int64_t nprime, int64_t nkb) {
+  (void)S;
+  (void)m;
+  (void)nprime;
+  (void)nkb;
+  static int env = -2;
+  if (env == -2) {
+    const char *e = getenv("OZAKI_GEMM_CONFIG");
+    env = (e != nullptr && *e) ? atoi(e) : -1;
+    if (env >= gemm_num_configs()) env = -1;
+  }
+  return env >= 0 ? env : 0;
+}
 
 // BLAS argument checks; returns 0 or -(argument number).
 int check_gemm_args(char transa, char transb, int64_t m, int64_t n, int64_t k, int64_t lda,
@@ -296,7 +313,8 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
   if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
   const GemmArgs ga = gemm_args(p, ws, ar, ai, br, bi, beta_zero, C, ldc, nullptr);
   const int mk = phase_begin(OZAKI_PHASE_GEMM, g.stream);
-  rc = hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+  rc = hip_rc(launch_ozgemm(slices, gemm_config(slices, m, p.nprime, p.nkb), ga,
+                            g.dev[dev].num_cu, g.stream));
   phase_end(mk, g.stream);
   if (g_tm.on) ++g_tm.calls;
   return rc;
@@ -537,7 +555,8 @@ int ozaki_debug_diagonals(char kind, char transa, char transb, int64_t m, int64_
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
   if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
   const GemmArgs ga = gemm_args(p, ws, 1.0, 0.0, 0.0, 0.0, true, nullptr, m, S);
-  return hip_rc(launch_ozgemm(slices, ga, g.dev[dev].num_cu, g.stream));
+  return hip_rc(launch_ozgemm(slices, gemm_config(slices, m, p.nprime, p.nkb), ga,
+                              g.dev[dev].num_cu, g.stream));
 }
 
 }  // extern "C"

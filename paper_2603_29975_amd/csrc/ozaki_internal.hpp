@@ -47,9 +47,12 @@ struct GemmArgs {
 // Contraction blocks (of 32) that one INT32 accumulation may cover for S
 // slices: S * 32 * kb * 127^2 < 2^31.
 int64_t kb_chunk_for(int S);
-// Bytes of int64 carry space the GEMM needs when nkb > kb_chunk.
-size_t gemm_flush_bytes(int S, int64_t m, int64_t nprime, int num_cu);
-hipError_t launch_ozgemm(int S, const GemmArgs &a, int num_cu, hipStream_t st);
+// Tile configurations of the fused GEMM (0 .. gemm_num_configs() - 1).
+int gemm_num_configs();
+// Bytes of int64 carry space the GEMM needs when nkb > kb_chunk (valid for
+// every configuration).
+size_t gemm_flush_bytes(int S, int cfg, int num_cu);
+hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
 
 // Native FP64 matrix-core GEMM.
 struct NativeArgs {
