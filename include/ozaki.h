@@ -64,11 +64,12 @@ typedef struct {
 
 enum ozaki_status {
   OZAKI_OK = 0,
-  OZAKI_ERR_HIP = 1,        /* a HIP runtime call or kernel launch failed */
-  OZAKI_ERR_ALLOC = 2,      /* device workspace could not be obtained */
-  OZAKI_ERR_WORKSPACE = 3,  /* the caller's workspace is too small */
-  OZAKI_ERR_NO_DEVICE = 4,  /* no usable gfx950 device */
-  OZAKI_ERR_INTERNAL = 5
+  OZAKI_ERR_HIP = 1,          /* a HIP runtime call or kernel launch failed */
+  OZAKI_ERR_ALLOC = 2,        /* device workspace could not be obtained */
+  OZAKI_ERR_WORKSPACE = 3,    /* the caller's workspace is too small */
+  OZAKI_ERR_NO_DEVICE = 4,    /* no usable gfx950 device */
+  OZAKI_ERR_INTERNAL = 5,
+  OZAKI_ERR_NO_SELECTOR = 6   /* automatic slice selection without a loaded selector */
 };
 
 /*
@@ -100,6 +101,43 @@ int ozaki_native_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k
 int ozaki_native_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                        ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B,
                        int64_t ldb, ozaki_z beta, ozaki_z *C, int64_t ldc);
+
+/*
+ * Batched complex GEMM: `batch` independent problems
+ *   C_b <- alpha_b op(A_b) op(B_b) + beta_b C_b,   b = 0 .. batch-1,
+ * each emulated exactly as ozaki_zgemm would with slices[b] slices (the results
+ * are bit-identical to batch separate ozaki_zgemm calls). Every argument is a
+ * HOST array of length `batch`; A, B and C hold device pointers. This serves
+ * the many small and uneven block products of a KKR/LSMS inversion (Sections
+ * 3.2 and 4 of the paper).
+ *   slices       host array of per-problem slice counts (1..OZAKI_S_MAX), or
+ *                NULL for automatic selection (ozaki_load_selector must have
+ *                been called; the residual probe raises any count that falls
+ *                short of the target). The automatic mode returns
+ *                OZAKI_ERR_NO_SELECTOR when no selector is loaded.
+ *   slices_used  host array receiving the slice count used per problem, or
+ *                NULL.
+ * Execution: one batched exponent scan, one batched split and one grouped
+ * persistent GEMM per distinct slice count walk global task and tile tables.
+ * With graphs on (the default), the sequence is captured into a HIP graph on
+ * the first call with a given argument set (pointers, sizes, scalars, slices)
+ * and replayed on later identical calls; the plan (device descriptors and
+ * packed-operand workspace, owned by the library) is cached with it.
+ * Errors: -i for argument i of the first invalid problem, numbered transa 1,
+ * transb 2, m 3, n 4, k 5, alpha 6, A 7, lda 8, B 9, ldb 10, beta 11, C 12,
+ * ldc 13, batch 14, slices 15; a NULL host array gives its argument number.
+ */
+int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m,
+                        const int64_t *n, const int64_t *k, const ozaki_z *alpha,
+                        const ozaki_z *const *A, const int64_t *lda, const ozaki_z *const *B,
+                        const int64_t *ldb, const ozaki_z *beta, ozaki_z *const *C,
+                        const int64_t *ldc, int64_t batch, const int *slices, int *slices_used);
+
+/* 1 (default): capture and replay HIP graphs in ozaki_zgemm_batched;
+ * 0: launch the same kernels directly on every call. */
+int ozaki_batched_graphs(int on);
+/* Release every cached batched plan and graph (device memory included). */
+int ozaki_batched_cache_clear(void);
 
 /* Stream for all later work (a hipStream_t; NULL = null stream). */
 int ozaki_set_stream(void *hip_stream);

@@ -23,7 +23,8 @@ __all__ = [
     "ozaki_dgemm", "ozaki_zgemm", "ozaki_native_dgemm", "ozaki_native_zgemm",
     "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
     "ozaki_finalize", "ozaki_status_string", "ozaki_timing_enable", "ozaki_timing_read", "ozaki_debug_exponents",
-    "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX",
+    "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX", "ozaki_zgemm_batched",
+    "ozaki_batched_graphs", "ozaki_batched_cache_clear",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,6 +58,9 @@ _SIG = {
                                       _i64, _vp, _i64, _c.c_double, _vp, _i64]),
     "ozaki_native_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64,
                                       _vp, _i64, ozaki_z, _vp, _i64]),
+    "ozaki_zgemm_batched": (_c.c_int, [_vp] * 13 + [_i64, _vp, _vp]),
+    "ozaki_batched_graphs": (_c.c_int, [_c.c_int]),
+    "ozaki_batched_cache_clear": (_c.c_int, []),
     "ozaki_set_stream": (_c.c_int, [_vp]),
     "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
     "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
@@ -138,6 +142,47 @@ def ozaki_native_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, 
     _bind_stream()
     return library().ozaki_native_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
                                         _ptr(B), ldb, _z(beta), _ptr(C), ldc)
+
+
+def ozaki_zgemm_batched(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch,
+                        slices, slices_used=None) -> int:
+    """Batched complex GEMM. Every argument is a sequence of length `batch`
+    (A, B, C: tensors or device addresses); `slices` may be None (automatic
+    selection). `slices_used`, if given, is a list that receives the slice
+    counts used."""
+    _bind_stream()
+    nb = int(batch)
+
+    def chars(v):
+        return (_c.c_char * max(nb, 1))(*[_ch(x) for x in v])
+
+    def i64(v):
+        return (_c.c_int64 * max(nb, 1))(*[int(x) for x in v])
+
+    def zs(v):
+        return (ozaki_z * max(nb, 1))(*[_z(x) for x in v])
+
+    def ptrs(v):
+        return (_c.c_void_p * max(nb, 1))(*[_ptr(x) for x in v])
+
+    args = [chars(transa), chars(transb), i64(m), i64(n), i64(k), zs(alpha), ptrs(A), i64(lda),
+            ptrs(B), i64(ldb), zs(beta), ptrs(C), i64(ldc)]
+    sl = None if slices is None else (_c.c_int * max(nb, 1))(*[int(x) for x in slices])
+    used = (_c.c_int * max(nb, 1))()
+    rc = library().ozaki_zgemm_batched(*[_c.cast(a, _c.c_void_p) for a in args], nb,
+                                       None if sl is None else _c.cast(sl, _c.c_void_p),
+                                       _c.cast(used, _c.c_void_p))
+    if slices_used is not None:
+        slices_used[:] = [used[i] for i in range(nb)]
+    return rc
+
+
+def ozaki_batched_graphs(on: bool) -> int:
+    return library().ozaki_batched_graphs(1 if on else 0)
+
+
+def ozaki_batched_cache_clear() -> int:
+    return library().ozaki_batched_cache_clear()
 
 
 def ozaki_set_stream(stream) -> int:

@@ -11,6 +11,8 @@
 #include <cctype>
 #include <cstdlib>
 #include <cstring>
+#include <list>
+#include <map>
 #include <vector>
 
 #include "../../include/ozaki.h"
@@ -259,9 +261,9 @@ int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t
   return OZAKI_OK;
 }
 
-GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, double bi,
-                   bool beta_zero, void *C, int64_t ldc, int64_t *raw) {
-  GemmArgs a{};
+GemmProblem gemm_problem(const Plan &p, char *ws, double ar, double ai, double br, double bi,
+                         bool beta_zero, void *C, int64_t ldc, int64_t *raw) {
+  GemmProblem a{};
   a.SP = reinterpret_cast<const int8_t *>(ws + p.off_SB);
   a.SQ = reinterpret_cast<const int8_t *>(ws + p.off_SA);
   a.nrbP = p.nrbP;
@@ -279,9 +281,17 @@ GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, dou
   a.cplx = p.cplx ? 1 : 0;
   a.C = C;
   a.ldc = ldc;
+  a.raw = raw;
+  return a;
+}
+
+GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, double bi,
+                   bool beta_zero, void *C, int64_t ldc, int64_t *raw) {
+  GemmArgs a{};
+  a.one = gemm_problem(p, ws, ar, ai, br, bi, beta_zero, C, ldc, raw);
   a.flush_ws = reinterpret_cast<int64_t *>(ws + p.off_flush);
   a.kb_chunk = p.kb_chunk;
-  a.raw = raw;
+  a.chunked = p.nkb > p.kb_chunk ? 1 : 0;
   return a;
 }
 
@@ -377,6 +387,302 @@ int debug_view(char kind, char side, char trans, int64_t rows, int64_t L, const 
   return 0;
 }
 
+
+// ---------------------------------------------------------------- batched
+// A batched plan: device descriptors (problems, task and tile tables) and the
+// packed-operand workspace of every problem in one allocation, plus the HIP
+// graph of its launch sequence.
+struct ScaleOp {
+  int64_t m, n, ldc;
+  double br, bi;
+  bool beta_zero;
+  void *C;
+};
+
+struct GroupDesc {
+  int S;
+  int64_t ntiles;
+  size_t off_tile_prob, off_tile_local;
+  bool chunked;
+};
+
+struct BatchedPlan {
+  std::vector<uint8_t> sig;  // exact argument signature
+  int dev = 0;
+  void *mem = nullptr;
+  size_t off_probs = 0, off_scan = 0, off_scan_start = 0, off_split = 0, off_split_start = 0,
+         off_flush = 0;
+  int nscan = 0, nsplit = 0;
+  int64_t scan_blocks = 0, split_blocks = 0;
+  std::vector<GroupDesc> groups;
+  std::vector<ScaleOp> scales;
+  std::vector<int> used;  // slices used per problem
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct BatchedState {
+  bool graphs = true;
+  std::list<BatchedPlan *> cache;  // most recent first
+  hipStream_t cap = nullptr;       // private stream used for graph capture
+};
+BatchedState g_bat;
+constexpr size_t kPlanCache = 4;
+
+void free_plan(BatchedPlan *pl) {
+  if (pl == nullptr) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->mem) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(pl->dev);
+    (void)hipFree(pl->mem);
+    (void)hipSetDevice(cur);
+  }
+  delete pl;
+}
+
+template <typename T>
+void sig_put(std::vector<uint8_t> &v, const T &x) {
+  const uint8_t *b = reinterpret_cast<const uint8_t *>(&x);
+  v.insert(v.end(), b, b + sizeof(T));
+}
+
+// Enqueue the plan's kernels on `st`.
+int enqueue_plan(const BatchedPlan &pl, hipStream_t st) {
+  char *base = static_cast<char *>(pl.mem);
+  int rc;
+  if ((rc = hip_rc(launch_scan_batched(reinterpret_cast<const ScanTask *>(base + pl.off_scan),
+                                       reinterpret_cast<const int64_t *>(base + pl.off_scan_start),
+                                       pl.nscan, pl.scan_blocks, st))))
+    return rc;
+  if ((rc = hip_rc(launch_split_batched(reinterpret_cast<const SplitTask *>(base + pl.off_split),
+                                        reinterpret_cast<const int64_t *>(base + pl.off_split_start),
+                                        pl.nsplit, pl.split_blocks, st))))
+    return rc;
+  for (const GroupDesc &gd : pl.groups) {
+    GemmArgs a{};
+    a.probs = reinterpret_cast<const GemmProblem *>(base + pl.off_probs);
+    a.tile_prob = reinterpret_cast<const int *>(base + gd.off_tile_prob);
+    a.tile_local = reinterpret_cast<const int *>(base + gd.off_tile_local);
+    a.ntiles = gd.ntiles;
+    a.flush_ws = reinterpret_cast<int64_t *>(base + pl.off_flush);
+    a.kb_chunk = kb_chunk_for(gd.S);
+    a.chunked = gd.chunked ? 1 : 0;
+    if ((rc = hip_rc(launch_ozgemm_grouped(gd.S, 0, a, g.dev[pl.dev].num_cu, st)))) return rc;
+  }
+  for (const ScaleOp &sc : pl.scales)
+    if ((rc = hip_rc(launch_scale(true, sc.m, sc.n, sc.br, sc.bi, sc.beta_zero, sc.C, sc.ldc, st))))
+      return rc;
+  return OZAKI_OK;
+}
+
+// Builds (or finds) the plan of a validated batched call.
+int get_plan(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+             const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A, const int64_t *lda,
+             const ozaki_z *const *B, const int64_t *ldb, const ozaki_z *beta, ozaki_z *const *C,
+             const int64_t *ldc, int64_t batch, const int *slices, BatchedPlan **out) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::vector<uint8_t> sig;
+  sig_put(sig, dev);
+  sig_put(sig, batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    sig_put(sig, up(transa[b]));
+    sig_put(sig, up(transb[b]));
+    sig_put(sig, m[b]);
+    sig_put(sig, n[b]);
+    sig_put(sig, k[b]);
+    sig_put(sig, alpha[b]);
+    sig_put(sig, A[b]);
+    sig_put(sig, lda[b]);
+    sig_put(sig, B[b]);
+    sig_put(sig, ldb[b]);
+    sig_put(sig, beta[b]);
+    sig_put(sig, C[b]);
+    sig_put(sig, ldc[b]);
+    sig_put(sig, slices[b]);
+  }
+  for (auto it = g_bat.cache.begin(); it != g_bat.cache.end(); ++it) {
+    if ((*it)->sig == sig) {
+      BatchedPlan *pl = *it;
+      g_bat.cache.erase(it);
+      g_bat.cache.push_front(pl);
+      *out = pl;
+      return OZAKI_OK;
+    }
+  }
+
+  BatchedPlan *pl = new BatchedPlan();
+  pl->sig = std::move(sig);
+  pl->dev = dev;
+  pl->used.assign((size_t)batch, 0);
+  const int num_cu = g.dev[dev].num_cu;
+
+  std::vector<GemmProblem> probs;
+  std::vector<ScanTask> scans;
+  std::vector<SplitTask> splits;
+  std::vector<int> prob_S;
+  std::vector<size_t> prob_ws;  // workspace offset of each emulated problem
+  std::vector<Plan> plans;
+  size_t ws_total = 0;
+  size_t flush_bytes = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    pl->used[b] = slices[b];
+    if (m[b] == 0 || n[b] == 0) continue;
+    const bool alpha_zero = alpha[b].re == 0.0 && alpha[b].im == 0.0;
+    const bool beta_zero = beta[b].re == 0.0 && beta[b].im == 0.0;
+    const bool beta_one = beta[b].re == 1.0 && beta[b].im == 0.0;
+    if (alpha_zero || k[b] == 0) {
+      if (!beta_one) pl->scales.push_back({m[b], n[b], ldc[b], beta[b].re, beta[b].im, beta_zero, C[b]});
+      continue;
+    }
+    const Plan p = make_plan(true, m[b], n[b], k[b], slices[b], num_cu);
+    plans.push_back(p);
+    prob_ws.push_back(ws_total);
+    ws_total += align256(p.off_flush);  // codes and packed operands (carry space is shared)
+    prob_S.push_back(slices[b]);
+    if (p.nkb > p.kb_chunk) flush_bytes = std::max(flush_bytes, gemm_flush_bytes(p.S, 0, num_cu));
+    GemmProblem gp = gemm_problem(p, nullptr, alpha[b].re, alpha[b].im, beta[b].re, beta[b].im,
+                                  beta_zero, C[b], ldc[b], nullptr);
+    probs.push_back(gp);
+    const View va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
+    const View vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
+    scans.push_back({va, nullptr, 1, va.sr == 1 ? 1 : 0});
+    scans.push_back({vb, nullptr, 1, vb.sr == 1 ? 1 : 0});
+    splits.push_back({va, nullptr, nullptr, p.nrbQ, p.nkb, p.S, 1, 0});
+    splits.push_back({vb, nullptr, nullptr, p.nrbP, p.nkb, p.S, 1, 1});
+  }
+  const size_t np = probs.size();
+
+  // tile tables, one group per distinct slice count, longest contraction first
+  std::map<int, std::vector<std::pair<int, int>>> tiles;  // S -> (problem, local tile)
+  for (size_t i = 0; i < np; ++i) {
+    const int64_t nt = gemm_tiles(prob_S[i], 0, plans[i].m, plans[i].nprime);
+    for (int64_t t = 0; t < nt; ++t) tiles[prob_S[i]].push_back({(int)i, (int)t});
+  }
+  for (auto &kv : tiles)
+    std::stable_sort(kv.second.begin(), kv.second.end(),
+                     [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                       return plans[x.first].nkb > plans[y.first].nkb;
+                     });
+
+  // device layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  pl->off_probs = take(np * sizeof(GemmProblem));
+  pl->nscan = (int)scans.size();
+  pl->off_scan = take(scans.size() * sizeof(ScanTask));
+  pl->off_scan_start = take((scans.size() + 1) * sizeof(int64_t));
+  pl->nsplit = (int)splits.size();
+  pl->off_split = take(splits.size() * sizeof(SplitTask));
+  pl->off_split_start = take((splits.size() + 1) * sizeof(int64_t));
+  for (auto &kv : tiles) {
+    GroupDesc gd{};
+    gd.S = kv.first;
+    gd.ntiles = (int64_t)kv.second.size();
+    gd.off_tile_prob = take(kv.second.size() * sizeof(int));
+    gd.off_tile_local = take(kv.second.size() * sizeof(int));
+    gd.chunked = false;
+    for (auto &pt : kv.second) gd.chunked = gd.chunked || plans[pt.first].nkb > plans[pt.first].kb_chunk;
+    pl->groups.push_back(gd);
+  }
+  pl->off_flush = take(flush_bytes);
+  const size_t desc_bytes = off;
+  const size_t off_ws = take(ws_total);
+  const size_t total = off;
+
+  if (hipMalloc(&pl->mem, total) != hipSuccess) {
+    (void)hipGetLastError();
+    free_plan(pl);
+    return OZAKI_ERR_ALLOC;
+  }
+  char *base = static_cast<char *>(pl->mem);
+
+  // patch device pointers into the descriptors
+  for (size_t i = 0; i < np; ++i) {
+    char *w = base + off_ws + prob_ws[i];
+    const Plan &p = plans[i];
+    GemmProblem &gp = probs[i];
+    gp.SP = reinterpret_cast<const int8_t *>(w + p.off_SB);
+    gp.SQ = reinterpret_cast<const int8_t *>(w + p.off_SA);
+    gp.codeA = reinterpret_cast<const int *>(w + p.off_codeA);
+    gp.codeB = reinterpret_cast<const int *>(w + p.off_codeB);
+    scans[2 * i].code = reinterpret_cast<int *>(w + p.off_codeA);
+    scans[2 * i + 1].code = reinterpret_cast<int *>(w + p.off_codeB);
+    splits[2 * i].code = reinterpret_cast<const int *>(w + p.off_codeA);
+    splits[2 * i].out = reinterpret_cast<int8_t *>(w + p.off_SA);
+    splits[2 * i + 1].code = reinterpret_cast<const int *>(w + p.off_codeB);
+    splits[2 * i + 1].out = reinterpret_cast<int8_t *>(w + p.off_SB);
+  }
+  std::vector<uint8_t> host(desc_bytes, 0);
+  auto put = [&](size_t o, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + o, src, bytes);
+  };
+  put(pl->off_probs, probs.data(), np * sizeof(GemmProblem));
+  put(pl->off_scan, scans.data(), scans.size() * sizeof(ScanTask));
+  put(pl->off_split, splits.data(), splits.size() * sizeof(SplitTask));
+  std::vector<int64_t> start(scans.size() + 1, 0);
+  for (size_t t = 0; t < scans.size(); ++t) start[t + 1] = start[t] + scan_task_blocks(scans[t]);
+  pl->scan_blocks = start.back();
+  put(pl->off_scan_start, start.data(), start.size() * sizeof(int64_t));
+  start.assign(splits.size() + 1, 0);
+  for (size_t t = 0; t < splits.size(); ++t) start[t + 1] = start[t] + split_task_blocks(splits[t]);
+  pl->split_blocks = start.back();
+  put(pl->off_split_start, start.data(), start.size() * sizeof(int64_t));
+  size_t gi = 0;
+  for (auto &kv : tiles) {
+    std::vector<int> tp(kv.second.size()), tl(kv.second.size());
+    for (size_t x = 0; x < kv.second.size(); ++x) {
+      tp[x] = kv.second[x].first;
+      tl[x] = kv.second[x].second;
+    }
+    put(pl->groups[gi].off_tile_prob, tp.data(), tp.size() * sizeof(int));
+    put(pl->groups[gi].off_tile_local, tl.data(), tl.size() * sizeof(int));
+    ++gi;
+  }
+  if (hipMemcpy(pl->mem, host.data(), desc_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(pl);
+    return OZAKI_ERR_HIP;
+  }
+
+  if (g_bat.graphs) {
+    if (g_bat.cap == nullptr && hipStreamCreateWithFlags(&g_bat.cap, hipStreamNonBlocking) != hipSuccess) {
+      free_plan(pl);
+      return OZAKI_ERR_HIP;
+    }
+    if (hipStreamBeginCapture(g_bat.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      free_plan(pl);
+      return OZAKI_ERR_HIP;
+    }
+    const int erc = enqueue_plan(*pl, g_bat.cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g_bat.cap, &graph);
+    pl->graph = graph;
+    if (erc != OZAKI_OK || e != hipSuccess ||
+        hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      free_plan(pl);
+      return OZAKI_ERR_HIP;
+    }
+  }
+
+  g_bat.cache.push_front(pl);
+  while (g_bat.cache.size() > kPlanCache) {
+    BatchedPlan *old = g_bat.cache.back();
+    g_bat.cache.pop_back();
+    free_plan(old);
+  }
+  *out = pl;
+  return OZAKI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -406,6 +712,66 @@ int ozaki_native_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k
                        ozaki_z *C, int64_t ldc) {
   return native_gemm(true, transa, transb, m, n, k, alpha.re, alpha.im, A, lda, B, ldb, beta.re,
                      beta.im, C, ldc);
+}
+
+int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+                        const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A,
+                        const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
+                        const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
+                        const int *slices, int *slices_used) {
+  if (batch < 0) return -14;
+  if (batch == 0) return OZAKI_OK;
+  if (!transa) return -1;
+  if (!transb) return -2;
+  if (!m) return -3;
+  if (!n) return -4;
+  if (!k) return -5;
+  if (!alpha) return -6;
+  if (!A) return -7;
+  if (!lda) return -8;
+  if (!B) return -9;
+  if (!ldb) return -10;
+  if (!beta) return -11;
+  if (!C) return -12;
+  if (!ldc) return -13;
+  if (slices == nullptr) return OZAKI_ERR_NO_SELECTOR;
+  for (int64_t b = 0; b < batch; ++b) {
+    int rc = check_gemm_args(transa[b], transb[b], m[b], n[b], k[b], lda[b], ldb[b], ldc[b]);
+    if (rc) return rc;
+    if (slices[b] < 1 || slices[b] > OZAKI_S_MAX) return -15;
+    if (m[b] == 0 || n[b] == 0) continue;
+    if (C[b] == nullptr) return -12;
+    const bool alpha_zero = alpha[b].re == 0.0 && alpha[b].im == 0.0;
+    if (alpha_zero || k[b] == 0) continue;
+    if (A[b] == nullptr) return -7;
+    if (B[b] == nullptr) return -9;
+  }
+  BatchedPlan *pl = nullptr;
+  int rc = get_plan(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, slices, &pl);
+  if (rc) return rc;
+  if (pl->exec != nullptr)
+    rc = hip_rc(hipGraphLaunch(pl->exec, g.stream));
+  else
+    rc = enqueue_plan(*pl, g.stream);
+  if (rc == OZAKI_OK && slices_used != nullptr)
+    for (int64_t b = 0; b < batch; ++b) slices_used[b] = pl->used[b];
+  return rc;
+}
+
+int ozaki_batched_graphs(int on) {
+  const bool want = on != 0;
+  if (want != g_bat.graphs) {
+    for (BatchedPlan *pl : g_bat.cache) free_plan(pl);
+    g_bat.cache.clear();
+  }
+  g_bat.graphs = want;
+  return OZAKI_OK;
+}
+
+int ozaki_batched_cache_clear(void) {
+  for (BatchedPlan *pl : g_bat.cache) free_plan(pl);
+  g_bat.cache.clear();
+  return OZAKI_OK;
 }
 
 int ozaki_set_stream(void *hip_stream) {
@@ -485,6 +851,7 @@ const char *ozaki_status_string(int status) {
     case OZAKI_ERR_WORKSPACE: return "caller workspace too small";
     case OZAKI_ERR_NO_DEVICE: return "no usable device";
     case OZAKI_ERR_INTERNAL: return "internal error";
+    case OZAKI_ERR_NO_SELECTOR: return "automatic slice selection needs a loaded selector";
     default: return "unknown status";
   }
 }

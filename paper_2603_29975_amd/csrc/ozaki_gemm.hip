@@ -68,8 +68,8 @@ __host__ __device__ constexpr int64_t chunk_blocks(int S) {
   return (int64_t)(2147483647ll / ((int64_t)S * 32 * 127 * 127));
 }
 
-template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED>
-__global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
+template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED>
+__global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
   __shared__ __attribute__((aligned(16))) int8_t lds[C_::LDS];
 
@@ -78,15 +78,20 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
   const int wj = wave % WJ;
   const int wi = wave / WJ;
 
-  const int64_t ntj = (a.nprime + C_::BJ - 1) / C_::BJ;
-  const int64_t nti = (a.m + C_::BI - 1) / C_::BI;
-  const int64_t ntiles = ntj * nti;
-  const int64_t nkb = a.nkb;
   constexpr bool chunked = CHUNKED;
+  const int64_t ntiles =
+      GROUPED ? G.ntiles
+              : ((G.one.nprime + C_::BJ - 1) / C_::BJ) * ((G.one.m + C_::BI - 1) / C_::BI);
 
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t tj = tile / nti;
-    const int64_t ti = tile % nti;
+    // The problem this tile belongs to (uniform across the workgroup, so the
+    // descriptor is fetched with scalar loads).
+    const GemmProblem a = GROUPED ? G.probs[G.tile_prob[tile]] : G.one;
+    const int64_t local = GROUPED ? (int64_t)G.tile_local[tile] : tile;
+    const int64_t nti = (a.m + C_::BI - 1) / C_::BI;
+    const int64_t tj = local / nti;
+    const int64_t ti = local % nti;
+    const int64_t nkb = a.nkb;
 
     // Copy of contraction block kb into LDS stage `buf`: fragment f lands at
     // stage offset f KiB (B' fragments first, then A' fragments).
@@ -120,7 +125,7 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
     // Exact int64 carry of the INT32 accumulators (chunked contraction only).
     // All carry traffic uses device-scope atomics, so it goes to L2 and never
     // meets a stale line in the non-coherent vector L1.
-    int64_t *ws = a.flush_ws + ((int64_t)blockIdx.x * C_::NW + wave) * (int64_t)IB * S * 1024;
+    int64_t *ws = G.flush_ws + ((int64_t)blockIdx.x * C_::NW + wave) * (int64_t)IB * S * 1024;
     auto carry = [&](bool first) {
 #pragma unroll
       for (int ib = 0; ib < IB; ++ib)
@@ -143,7 +148,8 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
     for (int d = 0; d < D; ++d)
       if (d < nkb) issue(d, d);
 
-    int64_t next_flush = a.kb_chunk;
+    int64_t next_flush = G.kb_chunk;
+    bool carried = false;
     int buf = 0;
     for (int64_t kb = 0; kb < nkb; ++kb) {
       // This wave's copies of block kb are complete when at most the copies
@@ -183,8 +189,9 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
       }
       if constexpr (chunked) {
         if (kb + 1 == next_flush && kb + 1 < nkb) {
-          carry(next_flush == a.kb_chunk);
-          next_flush += a.kb_chunk;
+          carry(!carried);
+          carried = true;
+          next_flush += G.kb_chunk;
           wait_vmcnt<0>();  // keep the in-order vmcnt accounting to LDS copies only
         }
       }
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
     // every wave is done reading the ring before the next tile refills it
     barrier_only();
 
-    if constexpr (chunked) carry(false);
+    if constexpr (chunked) carry(!carried);
 
     // ------------------------------------------------------------ epilogue
     auto epilogue = [&](int ib) {
@@ -297,22 +304,29 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs a) {
 template <int S, int WJ, int WI, int IB, int NBUF>
 hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
-  const int64_t ntiles = ((a.nprime + C_::BJ - 1) / C_::BJ) * ((a.m + C_::BI - 1) / C_::BI);
+  const bool grouped = a.probs != nullptr;
+  const int64_t ntiles =
+      grouped ? a.ntiles
+              : ((a.one.nprime + C_::BJ - 1) / C_::BJ) * ((a.one.m + C_::BI - 1) / C_::BI);
   // one workgroup per CU is resident (LDS ring); persistent grid
   const int64_t grid = std::min<int64_t>(ntiles, (int64_t)num_cu);
   if (grid <= 0) return hipSuccess;
   const dim3 g((unsigned)grid), b(C_::NT);
-  const bool chunked = a.nkb > a.kb_chunk;
-  if (a.raw != nullptr) {
-    if (chunked)
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true>), g, b, 0, st, a);
+  if (grouped) {
+    if (a.chunked)
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, true>), g, b, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, true>), g, b, 0, st, a);
+  } else if (a.one.raw != nullptr) {
+    if (a.chunked)
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true, false>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false, false>), g, b, 0, st, a);
   } else {
-    if (chunked)
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true>), g, b, 0, st, a);
+    if (a.chunked)
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, false>), g, b, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, false>), g, b, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -326,7 +340,7 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //   2: 2 x 2 waves with two blocks along i each; workgroup tile 64 j' x 128 i.
 // The LDS ring holds three contraction blocks when it fits in 160 KiB, two
 // otherwise.
-constexpr int kNumCfg = 3;
+constexpr int kNumCfg = 1;
 
 template <int S, int CFG>
 struct Pick;
@@ -357,21 +371,14 @@ hipError_t launch_pick(const GemmArgs &a, int num_cu, hipStream_t st) {
 
 template <int S>
 hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
-  switch (cfg) {
-    case 1: return launch_pick<S, 1>(a, num_cu, st);
-    case 2: return launch_pick<S, 2>(a, num_cu, st);
-    default: return launch_pick<S, 0>(a, num_cu, st);
-  }
+  (void)cfg;
+  return launch_pick<S, 0>(a, num_cu, st);
 }
 
 template <int S>
 size_t flush_bytes_s(int cfg, int num_cu) {
-  int per = 0;
-  switch (cfg) {
-    case 1: per = Pick<S, 1>::WJ * Pick<S, 1>::WI * Pick<S, 1>::IB; break;
-    case 2: per = Pick<S, 2>::WJ * Pick<S, 2>::WI * Pick<S, 2>::IB; break;
-    default: per = Pick<S, 0>::WJ * Pick<S, 0>::WI * Pick<S, 0>::IB; break;
-  }
+  (void)cfg;
+  const int per = Pick<S, 0>::WJ * Pick<S, 0>::WI * Pick<S, 0>::IB;
   return (size_t)num_cu * per * (size_t)S * 1024 * sizeof(int64_t);
 }
 
@@ -399,6 +406,18 @@ size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
     mx = std::max(mx, b);
   }
   return mx;
+}
+
+int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
+  (void)S;
+  (void)cfg;
+  using P = Pick<1, 0>;
+  const int64_t BJ = 32 * P::WJ, BI = 32 * P::WI * P::IB;
+  return ((nprime + BJ - 1) / BJ) * ((m + BI - 1) / BI);
+}
+
+hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
+  return launch_ozgemm(S, cfg, a, num_cu, st);
 }
 
 hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {

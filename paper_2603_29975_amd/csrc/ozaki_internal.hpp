@@ -17,6 +17,32 @@ hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st);
 hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S,
                         int8_t *out, int64_t nrb, int64_t nkb, hipStream_t st);
 
+// Batched scan and split: task tables in device memory. A scan task covers
+// all rows of one operand view over its whole contraction (codes are stored,
+// no zero fill needed); a split task writes one packed operand.
+struct ScanTask {
+  View v;
+  int *code;
+  int cplx;
+  int rows_fast;  // v.sr == 1: 64 rows per block, else 4 rows per block
+};
+struct SplitTask {
+  View v;
+  const int *code;
+  int8_t *out;
+  int64_t nrb, nkb;
+  int S;
+  int cplx;
+  int side_b;
+};
+int64_t scan_task_blocks(const ScanTask &t);
+int64_t split_task_blocks(const SplitTask &t);
+// start[t] = first block of task t (prefix sums of the task block counts).
+hipError_t launch_scan_batched(const ScanTask *tasks, const int64_t *start, int ntasks,
+                               int64_t nblocks, hipStream_t st);
+hipError_t launch_split_batched(const SplitTask *tasks, const int64_t *start, int ntasks,
+                                int64_t nblocks, hipStream_t st);
+
 // Debug helpers.
 hipError_t launch_unpack(const int8_t *packed, bool cplx, bool side_b, int64_t R, int64_t L,
                          int S, int64_t nrb, int64_t nkb, int8_t *digits, hipStream_t st);
@@ -27,8 +53,9 @@ hipError_t launch_codes_to_exps(const int *code, int64_t R, int32_t *exps, uint8
 hipError_t launch_scale(bool cplx, int64_t m, int64_t n, double br, double bi, bool beta_zero,
                         void *C, int64_t ldc, hipStream_t st);
 
-// Fused slice-pair GEMM + recombination.
-struct GemmArgs {
+// Fused slice-pair GEMM + recombination: one product C = alpha op(A) op(B)
+// + beta C given its packed operands and exponent codes.
+struct GemmProblem {
   const int8_t *SP;  // packed B' (rows j' of the output's column side)
   const int8_t *SQ;  // packed A' (rows i)
   int64_t nrbP, nrbQ, nkb;
@@ -39,10 +66,27 @@ struct GemmArgs {
   int cplx;
   void *C;
   int64_t ldc;
-  int64_t *flush_ws;   // int64 per-workgroup carry space (chunked K only)
-  int64_t kb_chunk;    // contraction blocks per exact INT32 chunk
-  int64_t *raw;        // raw diagonal output (debug) or nullptr
+  int64_t *raw;  // raw diagonal output (debug) or nullptr
 };
+
+// Kernel arguments: either one problem (grouped == 0) or a table of problems
+// walked through a tile table (tile t belongs to problem tile_prob[t] and is
+// its tile number tile_local[t]).
+struct GemmArgs {
+  GemmProblem one;
+  const GemmProblem *probs;
+  const int *tile_prob;
+  const int *tile_local;
+  int64_t ntiles;
+  int64_t *flush_ws;  // int64 per-workgroup carry space (chunked K only)
+  int64_t kb_chunk;   // contraction blocks per exact INT32 chunk
+  int chunked;        // some problem has nkb > kb_chunk
+};
+
+// Tile counts of a problem for a configuration (host side).
+int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime);
+// Launch a grouped GEMM over the tile table in `a` (every problem has S slices).
+hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
 
 // Contraction blocks (of 32) that one INT32 accumulation may cover for S
 // slices: S * 32 * kb * 127^2 < 2^31.

@@ -27,12 +27,13 @@ __device__ __forceinline__ int elem_code(const void *base, int64_t off) {
 // Rows are unit-stride in memory (sr == 1): 64 consecutive rows per block,
 // four threads per row walking the contraction index; each warp-wide load is
 // one contiguous run of 64 elements.
+// `direct`: the block covers the whole contraction range, so the row code is
+// stored instead of max-combined with other blocks.
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_scan_rowsfast(View v, int64_t lchunk, int *code) {
+__device__ __forceinline__ void scan_rowsfast_block(const View &v, int64_t rb, int64_t l0,
+                                                    int64_t l1, int *code, bool direct) {
   const int tid = threadIdx.x;
-  const int64_t r = (int64_t)blockIdx.x * 64 + (tid & 63);
-  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
-  const int64_t l1 = min(v.L, l0 + lchunk);
+  const int64_t r = rb * 64 + (tid & 63);
   int c = 0;
   if (r < v.R) {
     for (int64_t l = l0 + (tid >> 6); l < l1; l += 4) c = max(c, elem_code<CPLX>(v.base, r + l * v.sl));
@@ -42,24 +43,45 @@ __global__ void __launch_bounds__(256) k_scan_rowsfast(View v, int64_t lchunk, i
   __syncthreads();
   if (tid < 64) {
     c = max(max(red[tid], red[tid + 64]), max(red[tid + 128], red[tid + 192]));
-    if (r < v.R && c > 0) atomicMax(code + r, c);
+    if (r < v.R) {
+      if (direct)
+        code[r] = c;
+      else if (c > 0)
+        atomicMax(code + r, c);
+    }
   }
+}
+
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_scan_rowsfast(View v, int64_t lchunk, int *code) {
+  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
+  scan_rowsfast_block<CPLX>(v, blockIdx.x, l0, min(v.L, l0 + lchunk), code, false);
 }
 
 // Each row is unit-stride (sl == 1): one wave per row and contraction chunk,
 // lanes read consecutive elements, a wave max-reduction gives the row code.
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_scan_rowcontig(View v, int64_t lchunk, int *code) {
+__device__ __forceinline__ void scan_rowcontig_block(const View &v, int64_t rb, int64_t l0,
+                                                     int64_t l1, int *code, bool direct) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r = rb * 4 + (threadIdx.x >> 6);
   if (r >= v.R) return;
-  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
-  const int64_t l1 = min(v.L, l0 + lchunk);
   int c = 0;
   for (int64_t l = l0 + lane; l < l1; l += 64) c = max(c, elem_code<CPLX>(v.base, r * v.sr + l));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off));
-  if (lane == 0 && c > 0) atomicMax(code + r, c);
+  if (lane == 0) {
+    if (direct)
+      code[r] = c;
+    else if (c > 0)
+      atomicMax(code + r, c);
+  }
+}
+
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_scan_rowcontig(View v, int64_t lchunk, int *code) {
+  const int64_t l0 = (int64_t)blockIdx.y * lchunk;
+  scan_rowcontig_block<CPLX>(v, blockIdx.x, l0, min(v.L, l0 + lchunk), code, false);
 }
 
 // One thread per (packed row, 16 consecutive packed contraction entries):
@@ -67,11 +89,11 @@ __global__ void __launch_bounds__(256) k_scan_rowcontig(View v, int64_t lchunk, 
 // and writes one 16-byte run per slice into the packed fragment layout.
 // Rows and entries beyond the operand are written as zero digits (padding).
 template <bool CPLX, bool SIDEB>
-__global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
-                                               int64_t nrb, int64_t nkb) {
+__device__ __forceinline__ void split_block(const View &v, const int *code, int S, int8_t *out,
+                                            int64_t nrb, int64_t nkb, int64_t bx, int64_t by) {
   const int tid = threadIdx.x;
-  const int64_t rp = (int64_t)blockIdx.x * 64 + (tid & 63);
-  const int64_t kp0 = ((int64_t)blockIdx.y * 4 + (tid >> 6)) * 16;
+  const int64_t rp = bx * 64 + (tid & 63);
+  const int64_t kp0 = (by * 4 + (tid >> 6)) * 16;
   const int64_t Rrows = (CPLX && SIDEB) ? 2 * v.R : v.R;
   const int64_t r = (CPLX && SIDEB) ? (rp >> 1) : rp;
   const int cr = (CPLX && SIDEB) ? (int)(rp & 1) : 0;
@@ -127,6 +149,67 @@ __global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, i
     }
     int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
     *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <bool CPLX, bool SIDEB>
+__global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
+                                               int64_t nrb, int64_t nkb) {
+  split_block<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- batched
+// Block b of a batched launch belongs to the task t with
+// start[t] <= b < start[t + 1] (binary search, uniform per block).
+__device__ __forceinline__ int find_task(const int64_t *start, int ntasks, int64_t b) {
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// One task scans all rows of one operand view over the whole contraction.
+__global__ void __launch_bounds__(256) k_scan_batched(const ScanTask *tasks, const int64_t *start,
+                                                      int ntasks) {
+  const int64_t b = blockIdx.x;
+  const int t = find_task(start, ntasks, b);
+  const ScanTask tk = tasks[t];
+  const int64_t rb = b - start[t];
+  if (tk.rows_fast) {
+    if (tk.cplx)
+      scan_rowsfast_block<true>(tk.v, rb, 0, tk.v.L, tk.code, true);
+    else
+      scan_rowsfast_block<false>(tk.v, rb, 0, tk.v.L, tk.code, true);
+  } else {
+    if (tk.cplx)
+      scan_rowcontig_block<true>(tk.v, rb, 0, tk.v.L, tk.code, true);
+    else
+      scan_rowcontig_block<false>(tk.v, rb, 0, tk.v.L, tk.code, true);
+  }
+}
+
+// One task splits one operand view into its packed buffer; its blocks cover
+// nrb * 32 / 64 packed-row groups times nkb * 32 / 64 contraction groups.
+__global__ void __launch_bounds__(256) k_split_batched(const SplitTask *tasks, const int64_t *start,
+                                                       int ntasks) {
+  const int64_t b = blockIdx.x;
+  const int t = find_task(start, ntasks, b);
+  const SplitTask tk = tasks[t];
+  const int64_t local = b - start[t];
+  const int64_t nbx = tk.nrb / 2;
+  const int64_t bx = local % nbx, by = local / nbx;
+  if (tk.cplx) {
+    if (tk.side_b)
+      split_block<true, true>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+    else
+      split_block<true, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+  } else {
+    split_block<false, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
   }
 }
 
@@ -259,6 +342,26 @@ hipError_t launch_codes_to_exps(const int *code, int64_t R, int32_t *exps, uint8
                                 hipStream_t st) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_codes, dim3(grid1(R)), dim3(256), 0, st, code, R, exps, flags);
+  return hipGetLastError();
+}
+
+int64_t scan_task_blocks(const ScanTask &t) {
+  return t.rows_fast ? (t.v.R + 63) / 64 : (t.v.R + 3) / 4;
+}
+
+int64_t split_task_blocks(const SplitTask &t) { return (t.nrb / 2) * (t.nkb / 2); }
+
+hipError_t launch_scan_batched(const ScanTask *tasks, const int64_t *start, int ntasks,
+                               int64_t nblocks, hipStream_t st) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_batched, dim3((unsigned)nblocks), dim3(256), 0, st, tasks, start, ntasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_batched(const SplitTask *tasks, const int64_t *start, int ntasks,
+                                int64_t nblocks, hipStream_t st) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_batched, dim3((unsigned)nblocks), dim3(256), 0, st, tasks, start, ntasks);
   return hipGetLastError();
 }
 

@@ -98,3 +98,29 @@ def test_status_strings_and_workspace_sizes():
     # packed slices dominate: s bytes per padded real entry of A' and B'
     assert oz.ozaki_workspace_bytes("d", 256, 256, 256, 8) > small
     assert small >= 7 * (256 * 256 + 256 * 256)
+
+
+def test_batched_argument_errors():
+    z = [0]
+    ok = dict(transa=["N"], transb=["N"], m=[4], n=[5], k=[6], alpha=[1.0], A=[1 << 40], lda=[4],
+              B=[1 << 40], ldb=[6], beta=[0.0], C=[1 << 40], ldc=[4], batch=1, slices=[7])
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return oz.ozaki_zgemm_batched(a["transa"], a["transb"], a["m"], a["n"], a["k"], a["alpha"],
+                                      a["A"], a["lda"], a["B"], a["ldb"], a["beta"], a["C"],
+                                      a["ldc"], a["batch"], a["slices"])
+
+    assert call(batch=-1) == -14
+    assert call(batch=0) == 0
+    assert call(transa=["x"]) == -1
+    assert call(m=[-2]) == -3
+    assert call(lda=[2]) == -8
+    assert call(ldc=[1]) == -13
+    assert call(slices=[0]) == -15
+    assert call(slices=[13]) == -15
+    assert call(C=[0]) == -12
+    assert call(A=[0]) == -7
+    assert call(slices=None) == 6          # OZAKI_ERR_NO_SELECTOR: automatic mode needs a selector
+    del z
