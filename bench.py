@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--slices", type=int, default=7)
     ap.add_argument("--workload", default="kkr2048",
-                    choices=["kkr2048", "binade256", "ill4096", "ill16384"])
+                    choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (timing and accuracy check)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -115,6 +115,8 @@ def main():
     oz.library()   # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batched512":
+        return run_batched(args)
 
     wl = workload(args.workload)
     A, B = wl["A"], wl["B"]
@@ -238,6 +240,108 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()
+                    if p.get("user_api") == "blas"] or [1])
+    except Exception:   # noqa: BLE001
+        return os.cpu_count() or 1
+
+
+def run_batched(args):
+    """512 independent complex GEMMs (m, n, k in 32..1024, log-uniform; per
+    matrix exponent spread U[0, 20] binades; seed 1003) at fixed s in one
+    ozaki_zgemm_batched call: batched scan, batched split, grouped persistent
+    GEMM, replayed from a captured HIP graph."""
+    import numpy as np
+    import torch
+    import paper_2603_29975_amd as oz
+    from workloads import batched_problems
+
+    s = args.slices
+    probs, (ms, ns, ks) = batched_problems(512, 1003)
+    nb = len(probs)
+    log(f"workload batched512: {nb} problems, s={s}")
+    Ad = [torch.from_numpy(np.ascontiguousarray(A.T)).cuda() for A, _ in probs]
+    Bd = [torch.from_numpy(np.ascontiguousarray(B.T)).cuda() for _, B in probs]
+    Cd = [torch.zeros((int(n), int(m)), dtype=torch.complex128, device="cuda") for m, n in zip(ms, ns)]
+    flops = float(np.sum(8.0 * ms * ns * ks))
+    pairs = s * (s + 1) // 2
+    call_args = (["N"] * nb, ["N"] * nb, list(ms), list(ns), list(ks), [1.0] * nb, Ad, list(ms),
+                 Bd, list(ks), [0.0] * nb, Cd, list(ms), nb, [s] * nb)
+
+    def run():
+        rc = oz.ozaki_zgemm_batched(*call_args)
+        if rc != 0:
+            raise RuntimeError(f"ozaki_zgemm_batched: {oz.ozaki_status_string(rc)}")
+
+    def timed(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    # eager launches with per-phase events (same kernels as the graph)
+    oz.ozaki_batched_graphs(False)
+    for _ in range(args.warmup):
+        run()
+    oz.ozaki_timing_enable(True)
+    oz.ozaki_timing_read()
+    eager_ms = timed(args.steps)
+    rc, phase_ms, calls = oz.ozaki_timing_read()
+    oz.ozaki_timing_enable(False)
+    phases = {p: v / max(calls, 1) for p, v in phase_ms.items()}
+    # graph replay: the measured configuration
+    oz.ozaki_batched_graphs(True)
+    for _ in range(args.warmup):
+        run()
+    graph_ms = timed(args.steps)
+    value = flops / (graph_ms * 1e-3) / 1e12
+    log(f"batched: graph {graph_ms:.3f} ms  eager {eager_ms:.3f} ms  {value:.2f} eff TFLOP/s  "
+        f"phases {phases}")
+    achieved = pairs * flops / (phases["gemm"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_ozgemm grouped (persistent over all problems' tiles)",
+                "ops_per_launch": pairs * flops, "avg_launch_ms": round(phases["gemm"], 4),
+                "note": "INT8 ops counted as 2 per multiply-add, dense INT8 peak"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import ozaki
+        t0 = time.perf_counter()
+        done_flops = 0.0
+        cnt = 0
+        for b in range(nb):
+            A, B = probs[b]
+            ozaki.ozaki_gemm("N", "N", A, B, s)
+            done_flops += 8.0 * A.shape[0] * B.shape[1] * A.shape[1]
+            cnt += 1
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        t = time.perf_counter() - t0
+        cpu = {"value": round(done_flops / t / 1e12, 6), "unit": "TFLOP/s", "cores": blas_threads(),
+               "kind": "oracle",
+               "sample": f"oracle Ozaki model on the first {cnt} of the {nb} problems, s={s}, {t:.2f} s",
+               "host_cpus": os.cpu_count()}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "batched_zgemm_512", "problems": nb, "slices": s,
+                   "sum_8mnk": flops, "m_range": [int(ms.min()), int(ms.max())], "seed": 1003,
+                   "inputs": "m,n,k in 32..1024 (P(32j) ~ 1/j); per-matrix exponent spread "
+                             "U[0,20] binades"},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "eager_ms_per_step": round(eager_ms, 4), "graph_ms_per_step": round(graph_ms, 4),
+        "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
     """The oracle timed on a bounded sample (rows 0..ms-1 of op(A) against the
     whole op(B)), plus the accuracy check of the GPU result on sampled entries
@@ -245,12 +349,7 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
     import numpy as np
     import torch
     from oracle import dd, metrics, ozaki
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()
-                       if p.get("user_api") == "blas"] or [1])
-    except Exception:   # noqa: BLE001
-        threads = os.cpu_count() or 1
+    threads = blas_threads()
     A, B = wl["A"], wl["B"]
     torch.cuda.synchronize()
     C = Cd.cpu().numpy().T
@@ -293,6 +392,11 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
     fixed = max(t1 - per_row * r1, 0.0)
     rows = int(max(r2, min(m, (target_s - fixed) / per_row)))
     t = timed(rows)
+    reps = 1
+    while rows == m and t * (reps + 1) / reps < target_s and reps < 8:   # whole problem: repeat
+        t += timed(rows)
+        reps += 1
+    t /= reps
     flops = (8.0 if np.iscomplexobj(A) else 2.0) * rows * n * k
     cpu = {"value": round(flops / t / 1e12, 6), "unit": "TFLOP/s", "cores": int(threads),
            "kind": "oracle",

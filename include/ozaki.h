@@ -139,6 +139,24 @@ int ozaki_batched_graphs(int on);
 /* Release every cached batched plan and graph (device memory included). */
 int ozaki_batched_cache_clear(void);
 
+/*
+ * Randomized FP64 residual probe of a computed product C ~ op(A) op(B)
+ * (as left by a call with alpha = 1, beta = 0). For nvec sign vectors x_v
+ * (entries +-1 from the top bit of SplitMix64(seed + v*n + j), v < nvec) it
+ * computes r_v = C x_v - op(A)(op(B) x_v) with compensated (Dot2) sums and
+ * u = |op(A)| (|op(B)| 1) (complex modulus entrywise), and writes
+ *   est[i] = sqrt(mean_v |r_v,i|^2) * sqrt(n) / u_i      (device array, m doubles)
+ * an estimate of the componentwise error scale max_j |C - C*|_ij / (|A||B|)_ij
+ * of row i: est[i] is 0 when u_i = 0 and r = 0, +Inf when u_i = 0 and r != 0,
+ * NaN when an input is not finite. The selector's slice count is checked
+ * against it (ozaki_zgemm_batched with slices == NULL). kind 'd' or 'z'.
+ * Errors: kind -1, transa -2, transb -3, m -4, n -5, k -6, A -7, lda -8, B -9,
+ * ldb -10, C -11, ldc -12, nvec -13 (1..4), est -15.
+ */
+int ozaki_probe(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                const void *A, int64_t lda, const void *B, int64_t ldb, const void *C,
+                int64_t ldc, int nvec, uint64_t seed, double *est);
+
 /* Stream for all later work (a hipStream_t; NULL = null stream). */
 int ozaki_set_stream(void *hip_stream);
 

@@ -62,3 +62,30 @@ def to_float(v) -> float | complex:
     if isinstance(v, tuple):
         return complex(float(v[0]), float(v[1]))
     return float(v)
+
+
+def _dyadic_q(x):
+    """num / 2^d for a float or a Fraction with a power-of-two denominator."""
+    if isinstance(x, Fraction):
+        num, den = x.numerator, x.denominator
+    else:
+        num, den = float(x).as_integer_ratio()
+    d = den.bit_length() - 1
+    if den != 1 << d:
+        raise ValueError("not a dyadic rational")
+    return num, d
+
+
+def exact_dot_q(a, b) -> Fraction:
+    """sum_l a_l b_l exactly for floats and dyadic Fractions."""
+    terms = []
+    dmax = 0
+    for x, y in zip(a, b):
+        nx, dx = _dyadic_q(x)
+        ny, dy = _dyadic_q(y)
+        terms.append((nx * ny, dx + dy))
+        dmax = max(dmax, dx + dy)
+    total = 0
+    for num, d in terms:
+        total += num << (dmax - d)
+    return Fraction(total, 1 << dmax)

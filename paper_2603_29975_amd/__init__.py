@@ -24,7 +24,7 @@ __all__ = [
     "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
     "ozaki_finalize", "ozaki_status_string", "ozaki_timing_enable", "ozaki_timing_read", "ozaki_debug_exponents",
     "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX", "ozaki_zgemm_batched",
-    "ozaki_batched_graphs", "ozaki_batched_cache_clear",
+    "ozaki_batched_graphs", "ozaki_batched_cache_clear", "ozaki_probe",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,6 +61,8 @@ _SIG = {
     "ozaki_zgemm_batched": (_c.c_int, [_vp] * 13 + [_i64, _vp, _vp]),
     "ozaki_batched_graphs": (_c.c_int, [_c.c_int]),
     "ozaki_batched_cache_clear": (_c.c_int, []),
+    "ozaki_probe": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _i64, _vp, _i64, _vp,
+                               _i64, _vp, _i64, _c.c_int, _c.c_uint64, _vp]),
     "ozaki_set_stream": (_c.c_int, [_vp]),
     "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
     "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
@@ -183,6 +185,12 @@ def ozaki_batched_graphs(on: bool) -> int:
 
 def ozaki_batched_cache_clear() -> int:
     return library().ozaki_batched_cache_clear()
+
+
+def ozaki_probe(kind, transa, transb, m, n, k, A, lda, B, ldb, C, ldc, nvec, seed, est) -> int:
+    _bind_stream()
+    return library().ozaki_probe(_ch(kind), _ch(transa), _ch(transb), m, n, k, _ptr(A), lda, _ptr(B),
+                                 ldb, _ptr(C), ldc, int(nvec), int(seed) & (2 ** 64 - 1), _ptr(est))
 
 
 def ozaki_set_stream(stream) -> int:

@@ -450,17 +450,24 @@ void sig_put(std::vector<uint8_t> &v, const T &x) {
 }
 
 // Enqueue the plan's kernels on `st`.
-int enqueue_plan(const BatchedPlan &pl, hipStream_t st) {
+int enqueue_plan(const BatchedPlan &pl, hipStream_t st, bool capturing) {
   char *base = static_cast<char *>(pl.mem);
   int rc;
+  // phase events only when launching directly (never inside a graph capture)
+  const bool timed = !capturing;
+  int mk = timed ? phase_begin(OZAKI_PHASE_SCAN, st) : -1;
   if ((rc = hip_rc(launch_scan_batched(reinterpret_cast<const ScanTask *>(base + pl.off_scan),
                                        reinterpret_cast<const int64_t *>(base + pl.off_scan_start),
                                        pl.nscan, pl.scan_blocks, st))))
     return rc;
+  phase_end(mk, st);
+  mk = timed ? phase_begin(OZAKI_PHASE_SPLIT, st) : -1;
   if ((rc = hip_rc(launch_split_batched(reinterpret_cast<const SplitTask *>(base + pl.off_split),
                                         reinterpret_cast<const int64_t *>(base + pl.off_split_start),
                                         pl.nsplit, pl.split_blocks, st))))
     return rc;
+  phase_end(mk, st);
+  mk = timed ? phase_begin(OZAKI_PHASE_GEMM, st) : -1;
   for (const GroupDesc &gd : pl.groups) {
     GemmArgs a{};
     a.probs = reinterpret_cast<const GemmProblem *>(base + pl.off_probs);
@@ -472,6 +479,8 @@ int enqueue_plan(const BatchedPlan &pl, hipStream_t st) {
     a.chunked = gd.chunked ? 1 : 0;
     if ((rc = hip_rc(launch_ozgemm_grouped(gd.S, 0, a, g.dev[pl.dev].num_cu, st)))) return rc;
   }
+  phase_end(mk, st);
+  if (timed && g_tm.on) ++g_tm.calls;
   for (const ScaleOp &sc : pl.scales)
     if ((rc = hip_rc(launch_scale(true, sc.m, sc.n, sc.br, sc.bi, sc.beta_zero, sc.C, sc.ldc, st))))
       return rc;
@@ -661,7 +670,7 @@ int get_plan(const char *transa, const char *transb, const int64_t *m, const int
       free_plan(pl);
       return OZAKI_ERR_HIP;
     }
-    const int erc = enqueue_plan(*pl, g_bat.cap);
+    const int erc = enqueue_plan(*pl, g_bat.cap, true);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(g_bat.cap, &graph);
     pl->graph = graph;
@@ -752,7 +761,7 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
   if (pl->exec != nullptr)
     rc = hip_rc(hipGraphLaunch(pl->exec, g.stream));
   else
-    rc = enqueue_plan(*pl, g.stream);
+    rc = enqueue_plan(*pl, g.stream, false);
   if (rc == OZAKI_OK && slices_used != nullptr)
     for (int64_t b = 0; b < batch; ++b) slices_used[b] = pl->used[b];
   return rc;
@@ -772,6 +781,35 @@ int ozaki_batched_cache_clear(void) {
   for (BatchedPlan *pl : g_bat.cache) free_plan(pl);
   g_bat.cache.clear();
   return OZAKI_OK;
+}
+
+int ozaki_probe(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k, const void *A,
+                int64_t lda, const void *B, int64_t ldb, const void *C, int64_t ldc, int nvec,
+                uint64_t seed, double *est) {
+  kind = up(kind);
+  if (kind != 'D' && kind != 'Z') return -1;
+  const bool cplx = kind == 'Z';
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
+  if (rc) {
+    // GEMM numbering -> probe numbering (kind is argument 1 here)
+    switch (rc) {
+      case -8: return -8;
+      case -10: return -10;
+      case -13: return -12;
+      default: return rc - 1;
+    }
+  }
+  if (nvec < 1 || nvec > probe_max_vectors()) return -13;
+  if (m == 0) return OZAKI_OK;
+  if (est == nullptr) return -15;
+  if (n > 0 && C == nullptr) return -11;
+  if (k > 0 && A == nullptr) return -7;
+  if (k > 0 && n > 0 && B == nullptr) return -9;
+  void *wsv = nullptr;
+  if ((rc = get_workspace(probe_workspace_bytes(k), &wsv))) return rc;
+  const View va = view_opA(A, transa, m, k, lda, cplx);
+  const View vb = view_opB(B, transb, k, n, ldb, cplx);
+  return hip_rc(launch_probe(va, vb, cplx, C, ldc, m, n, k, nvec, seed, wsv, est, g.stream));
 }
 
 int ozaki_set_stream(void *hip_stream) {

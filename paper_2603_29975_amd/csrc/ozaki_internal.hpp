@@ -98,6 +98,13 @@ int gemm_num_configs();
 size_t gemm_flush_bytes(int S, int cfg, int num_cu);
 hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
 
+// Randomized residual probe (see ozaki_probe.hip).
+size_t probe_workspace_bytes(int64_t k);
+int probe_max_vectors();
+hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
+                        int64_t m, int64_t n, int64_t k, int nv, uint64_t seed, void *ws, double *est,
+                        hipStream_t st);
+
 // Native FP64 matrix-core GEMM.
 struct NativeArgs {
   View A;  // op(A): rows i, contraction l

@@ -88,7 +88,24 @@ __global__ void __launch_bounds__(256) k_scan_rowcontig(View v, int64_t lchunk, 
 // reads the 16 source values (8 complex elements), splits each into S digits
 // and writes one 16-byte run per slice into the packed fragment layout.
 // Rows and entries beyond the operand are written as zero digits (padding).
-template <bool CPLX, bool SIDEB>
+// Per-byte negation of four packed digits in [0, 127]: bytes whose mask byte
+// is 0xff become (-d) mod 256. (d ^ 0x7f) + 1 = 128 - d never carries out of
+// its byte, and xor 0x80 then adds 128.
+__device__ __forceinline__ uint32_t neg_bytes(uint32_t w, uint32_t mask) {
+  return ((w ^ (mask & 0x7f7f7f7fu)) + (mask & 0x01010101u)) ^ (mask & 0x80808080u);
+}
+
+// floor(|x| 2^(7S)) for S <= 9 (at most 63 bits): the top 7S bits of |x|
+// below the binary point as one integer, so digit p is bits
+// [7(S-p), 7(S-p)+7) of it.
+template <int S>
+__device__ __forceinline__ uint64_t top_bits(const Sig &x) {
+  const int sh = x.sh0 + kDigitBits * S;
+  if (sh >= 0) return x.m << sh;  // sh <= 7S - 53 <= 10: no overflow
+  return (sh > -64) ? (x.m >> (-sh)) : 0ull;
+}
+
+template <bool CPLX, bool SIDEB, int SC>
 __device__ __forceinline__ void split_block(const View &v, const int *code, int S, int8_t *out,
                                             int64_t nrb, int64_t nkb, int64_t bx, int64_t by) {
   const int tid = threadIdx.x;
@@ -138,24 +155,68 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
     }
   }
 
-  for (int p = 1; p <= S; ++p) {
-    uint32_t w[4];
+  if constexpr (SC > 0) {
+    // S known at compile time and 7S <= 63: one integer per value, digits by
+    // constant shifts, signs applied four bytes at a time.
+    uint64_t T[16];
+    uint32_t neg[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      uint32_t word = 0;
+      uint32_t mk = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) word |= ((uint32_t)digit(sg[4 * q + b], p) & 0xffu) << (8 * b);
-      w[q] = word;
+      for (int b = 0; b < 4; ++b) {
+        T[4 * q + b] = top_bits<SC>(sg[4 * q + b]);
+        mk |= (sg[4 * q + b].neg ? 0xffu : 0u) << (8 * b);
+      }
+      neg[q] = mk;
     }
-    int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
-    *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+    for (int p = 1; p <= SC; ++p) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          word |= ((uint32_t)(T[4 * q + b] >> (kDigitBits * (SC - p))) & 127u) << (8 * b);
+        w[q] = neg_bytes(word, neg[q]);
+      }
+      int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
+      *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  } else {
+    for (int p = 1; p <= S; ++p) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= ((uint32_t)digit(sg[4 * q + b], p) & 0xffu) << (8 * b);
+        w[q] = word;
+      }
+      int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
+      *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
+template <bool CPLX, bool SIDEB>
+__device__ __forceinline__ void split_dispatch(const View &v, const int *code, int S, int8_t *out,
+                                               int64_t nrb, int64_t nkb, int64_t bx, int64_t by) {
+  switch (S) {
+#define OZ_SPLIT(N) \
+  case N: split_block<CPLX, SIDEB, N>(v, code, S, out, nrb, nkb, bx, by); break;
+    OZ_SPLIT(1) OZ_SPLIT(2) OZ_SPLIT(3) OZ_SPLIT(4) OZ_SPLIT(5) OZ_SPLIT(6) OZ_SPLIT(7)
+    OZ_SPLIT(8) OZ_SPLIT(9)
+#undef OZ_SPLIT
+    default: split_block<CPLX, SIDEB, 0>(v, code, S, out, nrb, nkb, bx, by); break;
   }
 }
 
 template <bool CPLX, bool SIDEB>
 __global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
                                                int64_t nrb, int64_t nkb) {
-  split_block<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y);
+  split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- batched
@@ -205,11 +266,11 @@ __global__ void __launch_bounds__(256) k_split_batched(const SplitTask *tasks, c
   const int64_t bx = local % nbx, by = local / nbx;
   if (tk.cplx) {
     if (tk.side_b)
-      split_block<true, true>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+      split_dispatch<true, true>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
     else
-      split_block<true, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+      split_dispatch<true, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
   } else {
-    split_block<false, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+    split_dispatch<false, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
   }
 }
 

@@ -124,3 +124,17 @@ def test_batched_argument_errors():
     assert call(A=[0]) == -7
     assert call(slices=None) == 6          # OZAKI_ERR_NO_SELECTOR: automatic mode needs a selector
     del z
+
+
+def test_probe_argument_errors():
+    f = oz.ozaki_probe
+    assert f("x", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 1) == -1
+    assert f("d", "Q", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 1) == -2
+    assert f("d", "N", "Q", 2, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 1) == -3
+    assert f("d", "N", "N", -1, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 1) == -4
+    assert f("d", "N", "N", 2, 2, 2, 1, 1, 1, 2, 1, 2, 1, 0, 1) == -8
+    assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 1, 1, 2, 1, 0, 1) == -10
+    assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 1, 1, 0, 1) == -12
+    assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 5, 0, 1) == -13
+    assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 0) == -15
+    assert f("d", "N", "N", 0, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 0) == 0

@@ -453,3 +453,52 @@ def test_err_comp_zero_denominator_rule():
     bad = np.zeros((3, 3))
     bad[1, 1] = 1e-300
     assert metrics.err_comp(bad, hi, lo, den) == float("inf")
+
+
+# ------------------------------------------------------------ residual probe
+def test_splitmix64_reference_outputs(golden_dir):
+    from oracle.probe import splitmix64
+    vals = {}
+    for line in open(f"{golden_dir}/splitmix64.txt"):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = int(v, 16)
+    first = splitmix64(0)
+    second = splitmix64(0x9E3779B97F4A7C15)     # state after one step
+    assert first == vals["state0_output1"] and second == vals["state0_output2"]
+
+
+def test_probe_closed_form_planted_error():
+    # A = B = I (n x n), C = I + delta e_i e_j^T: r_v = delta x_v[j] e_i exactly,
+    # u = 1 for every row, so est_i = |delta| sqrt(n) and 0 elsewhere.
+    from oracle.probe import probe_est
+    n = 9
+    A = np.eye(n)
+    B = np.eye(n)
+    for delta in (2.0 ** -40, 3e-9):
+        C = np.eye(n)
+        C[4, 7] += delta
+        est = probe_est("N", "N", A, B, C, 3, seed=99)
+        want = np.zeros(n)
+        want[4] = abs(delta) * np.sqrt(n)          # C[4, 7] was 0: the planted entry is delta
+        assert np.allclose(est, want, rtol=1e-12, atol=0)
+
+
+def test_probe_invariant_under_row_scaling_and_tracks_error():
+    from oracle.probe import probe_est
+    A, B = uniform_binade(30, 24, 20, seed=70)
+    rng = np.random.default_rng(71)
+    r = rng.integers(-20, 21, 30)
+    C4 = ozaki.ozaki_gemm("N", "N", A, B, 4)
+    est = probe_est("N", "N", A, B, C4, 2, seed=5)
+    A2 = A * np.ldexp(1.0, r)[:, None]
+    C42 = ozaki.ozaki_gemm("N", "N", A2, B, 4)
+    est2 = probe_est("N", "N", A2, B, C42, 2, seed=5)
+    assert np.allclose(est, est2, rtol=1e-14)
+    # the estimate sits within a small factor of the true componentwise error
+    hi, lo = dd.dd_gemm("N", "N", A, B)
+    den = metrics.abs_product("N", "N", A, B)
+    true = metrics.err_comp(C4, hi, lo, den)
+    assert true / 30 < est.max() < true * 3
+    C7 = ozaki.ozaki_gemm("N", "N", A, B, 7)
+    assert probe_est("N", "N", A, B, C7, 2, seed=5).max() < est.max() / 1e4
