@@ -133,6 +133,20 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
                         const int64_t *ldb, const ozaki_z *beta, ozaki_z *const *C,
                         const int64_t *ldc, int64_t batch, const int *slices, int *slices_used);
 
+/*
+ * Selector for the automatic mode of ozaki_zgemm_batched (slices == NULL):
+ * params are the OZAKI_MLP_PARAMS FP32 MLP parameters (host array, copied).
+ * A problem gets s = ceil(prediction + margin) slices (clamped to 1..12); its
+ * product is formed with alpha = 1, beta = 0 in library memory and probed
+ * (ozaki_probe, 2 vectors); while max_i est[i] * kappa > target and s < 12,
+ * s rises by one and the product is redone. C is then finished with alpha and
+ * beta by the fused epilogue's formula, so the result equals ozaki_zgemm at the
+ * final s bit for bit. The automatic mode synchronises the stream (the slice
+ * counts are decided on the host) and is not captured into graphs.
+ * Errors: params -1, margin -2 (outside [-4, 8]), target -3 (<= 0), kappa -4 (< 1).
+ */
+int ozaki_load_selector(const float *params, float margin, double target, double kappa);
+
 /* 1 (default): capture and replay HIP graphs in ozaki_zgemm_batched;
  * 0: launch the same kernels directly on every call. */
 int ozaki_batched_graphs(int on);
@@ -156,6 +170,50 @@ int ozaki_batched_cache_clear(void);
 int ozaki_probe(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
                 const void *A, int64_t lda, const void *B, int64_t ldb, const void *C,
                 int64_t ldc, int nvec, uint64_t seed, double *est);
+
+/*
+ * Selector features of one product (64 floats, device array `feat`): the
+ * fraction of entries of op(A) lying delta = e_i - E(a_il) binades below their
+ * row maximum, bins min(delta, 30) and a last bin for zeros (32 values); the
+ * same over the columns of op(B), bins min(delta, 29) and zeros (31 values);
+ * log2(k) / 16. E is the frexp exponent (the larger of the real and imaginary
+ * parts for complex data). An entry delta binades down keeps 7s - delta of
+ * its bits, which is what the slice count has to cover; the paper notes that
+ * accuracy depends on both the precision and the operator (abstract).
+ * kind 'd' or 'z'; errors as ozaki_probe (kind -1, transa -2, transb -3, m -4,
+ * n -5, k -6, lda -8, ldb -10), feat -11.
+ */
+int ozaki_features(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                   const void *A, int64_t lda, const void *B, int64_t ldb, float *feat);
+
+/*
+ * Selector MLP: 64 -> 128 -> 128 -> 1 with ReLU, predicting the slice count
+ * a product needs from its features. OZAKI_MLP_PARAMS FP32 parameters in the
+ * order W1[128][64], b1[128], W2[128][128], b2[128], w3[128], b3; the matrix
+ * products run on BF16 matrix cores (weights and layer inputs rounded to BF16
+ * with round-to-nearest-even, FP32 accumulation).
+ * `state` is a caller-owned device buffer of ozaki_mlp_state_bytes() bytes:
+ * parameters at byte 0, Adam first and second moments and the gradient after
+ * them (OZAKI_MLP_PARAMS floats each, in that order), then BF16 copies.
+ * `scratch` is a device buffer of ozaki_mlp_scratch_bytes(batch) bytes; the
+ * backward pass reads the activations the forward pass left there.
+ *   init      He-uniform weights from SplitMix64(seed + index), zero biases
+ *   refresh   rebuild the BF16 copies after writing parameters directly
+ *   forward   y[b] for b < batch from X[b][64] (device, FP32)
+ *   backward  loss (1/B) sum w_b (y_b - t_b)^2, w_b = under_weight when
+ *             y_b < t_b else 1; writes the gradient into the state and the
+ *             loss into *loss (device scalar, may be NULL)
+ *   adam      one Adam step (bias-corrected, step >= 1) from the stored gradient
+ */
+#define OZAKI_MLP_PARAMS 24961
+size_t ozaki_mlp_state_bytes(void);
+size_t ozaki_mlp_scratch_bytes(int64_t batch);
+int ozaki_mlp_init(void *state, uint64_t seed);
+int ozaki_mlp_refresh(void *state);
+int ozaki_mlp_forward(const void *state, int64_t batch, const float *X, float *y, void *scratch);
+int ozaki_mlp_backward(void *state, int64_t batch, const float *y, const float *target,
+                       float under_weight, float *loss, void *scratch);
+int ozaki_mlp_adam(void *state, float lr, float beta1, float beta2, float eps, int64_t step);
 
 /* Stream for all later work (a hipStream_t; NULL = null stream). */
 int ozaki_set_stream(void *hip_stream);

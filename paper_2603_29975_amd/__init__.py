@@ -24,7 +24,10 @@ __all__ = [
     "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
     "ozaki_finalize", "ozaki_status_string", "ozaki_timing_enable", "ozaki_timing_read", "ozaki_debug_exponents",
     "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX", "ozaki_zgemm_batched",
-    "ozaki_batched_graphs", "ozaki_batched_cache_clear", "ozaki_probe",
+    "ozaki_batched_graphs", "ozaki_batched_cache_clear", "ozaki_probe", "ozaki_features",
+    "ozaki_mlp_state_bytes", "ozaki_mlp_scratch_bytes", "ozaki_mlp_init", "ozaki_mlp_refresh",
+    "ozaki_mlp_forward", "ozaki_mlp_backward", "ozaki_mlp_adam", "MLP_PARAMS",
+    "ozaki_load_selector",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -63,6 +66,16 @@ _SIG = {
     "ozaki_batched_cache_clear": (_c.c_int, []),
     "ozaki_probe": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _i64, _vp, _i64, _vp,
                                _i64, _vp, _i64, _c.c_int, _c.c_uint64, _vp]),
+    "ozaki_features": (_c.c_int, [_c.c_char, _c.c_char, _c.c_char, _i64, _i64, _i64, _vp, _i64,
+                                  _vp, _i64, _vp]),
+    "ozaki_mlp_state_bytes": (_c.c_size_t, []),
+    "ozaki_mlp_scratch_bytes": (_c.c_size_t, [_i64]),
+    "ozaki_mlp_init": (_c.c_int, [_vp, _c.c_uint64]),
+    "ozaki_mlp_refresh": (_c.c_int, [_vp]),
+    "ozaki_mlp_forward": (_c.c_int, [_vp, _i64, _vp, _vp, _vp]),
+    "ozaki_mlp_backward": (_c.c_int, [_vp, _i64, _vp, _vp, _c.c_float, _vp, _vp]),
+    "ozaki_mlp_adam": (_c.c_int, [_vp, _c.c_float, _c.c_float, _c.c_float, _c.c_float, _i64]),
+    "ozaki_load_selector": (_c.c_int, [_vp, _c.c_float, _c.c_double, _c.c_double]),
     "ozaki_set_stream": (_c.c_int, [_vp]),
     "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
     "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
@@ -191,6 +204,60 @@ def ozaki_probe(kind, transa, transb, m, n, k, A, lda, B, ldb, C, ldc, nvec, see
     _bind_stream()
     return library().ozaki_probe(_ch(kind), _ch(transa), _ch(transb), m, n, k, _ptr(A), lda, _ptr(B),
                                  ldb, _ptr(C), ldc, int(nvec), int(seed) & (2 ** 64 - 1), _ptr(est))
+
+
+MLP_PARAMS = 24961
+
+
+def ozaki_features(kind, transa, transb, m, n, k, A, lda, B, ldb, feat) -> int:
+    _bind_stream()
+    return library().ozaki_features(_ch(kind), _ch(transa), _ch(transb), m, n, k, _ptr(A), lda,
+                                    _ptr(B), ldb, _ptr(feat))
+
+
+def ozaki_mlp_state_bytes() -> int:
+    return library().ozaki_mlp_state_bytes()
+
+
+def ozaki_mlp_scratch_bytes(batch) -> int:
+    return library().ozaki_mlp_scratch_bytes(int(batch))
+
+
+def ozaki_mlp_init(state, seed) -> int:
+    _bind_stream()
+    return library().ozaki_mlp_init(_ptr(state), int(seed) & (2 ** 64 - 1))
+
+
+def ozaki_mlp_refresh(state) -> int:
+    _bind_stream()
+    return library().ozaki_mlp_refresh(_ptr(state))
+
+
+def ozaki_mlp_forward(state, batch, X, y, scratch) -> int:
+    _bind_stream()
+    return library().ozaki_mlp_forward(_ptr(state), int(batch), _ptr(X), _ptr(y), _ptr(scratch))
+
+
+def ozaki_mlp_backward(state, batch, y, target, under_weight, loss, scratch) -> int:
+    _bind_stream()
+    return library().ozaki_mlp_backward(_ptr(state), int(batch), _ptr(y), _ptr(target),
+                                         float(under_weight), _ptr(loss), _ptr(scratch))
+
+
+def ozaki_mlp_adam(state, lr, beta1, beta2, eps, step) -> int:
+    _bind_stream()
+    return library().ozaki_mlp_adam(_ptr(state), float(lr), float(beta1), float(beta2), float(eps),
+                                    int(step))
+
+
+def ozaki_load_selector(params, margin, target, kappa) -> int:
+    """params: a host sequence / numpy array of MLP_PARAMS floats."""
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if p.size != MLP_PARAMS:
+        return -1
+    return library().ozaki_load_selector(p.ctypes.data_as(_c.c_void_p), float(margin), float(target),
+                                         float(kappa))
 
 
 def ozaki_set_stream(stream) -> int:

@@ -9,6 +9,7 @@
 // emulation through intercepted standard BLAS calls (Section 3.1).
 #include <algorithm>
 #include <cctype>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <list>
@@ -692,6 +693,296 @@ int get_plan(const char *transa, const char *transb, const int64_t *m, const int
   return OZAKI_OK;
 }
 
+// Validated fixed-slice batched call: plan (cached) + graph replay or launches.
+int run_fixed_batched(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+                      const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A,
+                      const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
+                      const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
+                      const int *slices) {
+  BatchedPlan *pl = nullptr;
+  int rc = get_plan(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, slices, &pl);
+  if (rc) return rc;
+  if (pl->exec != nullptr) return hip_rc(hipGraphLaunch(pl->exec, g.stream));
+  return enqueue_plan(*pl, g.stream, false);
+}
+
+// ---------------------------------------------------------------- automatic slices
+struct SelectorState {
+  bool loaded = false;
+  int dev = -1;
+  void *state = nullptr;  // MLP state (device)
+  float margin = 0.5f;
+  double target = 1e-11;
+  double kappa = 8.0;     // probe estimate times kappa must meet the target
+  void *ws = nullptr;     // grow-only scratch of the automatic mode
+  size_t ws_bytes = 0;
+};
+SelectorState g_sel;
+
+int load_selector(const float *params, float margin, double target, double kappa) {
+  if (params == nullptr) return -1;
+  if (!(margin >= -4.0f && margin <= 8.0f)) return -2;
+  if (!(target > 0.0)) return -3;
+  if (!(kappa >= 1.0)) return -4;
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  if (g_sel.state != nullptr && g_sel.dev != dev) {
+    (void)hipFree(g_sel.state);
+    g_sel.state = nullptr;
+  }
+  if (g_sel.state == nullptr) {
+    if (hipMalloc(&g_sel.state, mlp_state_bytes()) != hipSuccess) {
+      (void)hipGetLastError();
+      return OZAKI_ERR_ALLOC;
+    }
+    if (hipMemset(g_sel.state, 0, mlp_state_bytes()) != hipSuccess) return OZAKI_ERR_HIP;
+  }
+  if (hipMemcpy(g_sel.state, params, sizeof(float) * mlp_params(), hipMemcpyHostToDevice) != hipSuccess)
+    return OZAKI_ERR_HIP;
+  if ((rc = hip_rc(mlp_refresh(g_sel.state, nullptr)))) return rc;
+  if (hipDeviceSynchronize() != hipSuccess) return OZAKI_ERR_HIP;
+  g_sel.dev = dev;
+  g_sel.margin = margin;
+  g_sel.target = target;
+  g_sel.kappa = kappa;
+  g_sel.loaded = true;
+  return OZAKI_OK;
+}
+
+int auto_ws(size_t bytes, char **out) {
+  if (g_sel.ws_bytes < bytes) {
+    if (g_sel.ws) (void)hipFree(g_sel.ws);
+    g_sel.ws = nullptr;
+    g_sel.ws_bytes = 0;
+    if (hipMalloc(&g_sel.ws, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return OZAKI_ERR_ALLOC;
+    }
+    g_sel.ws_bytes = bytes;
+  }
+  *out = static_cast<char *>(g_sel.ws);
+  return OZAKI_OK;
+}
+
+// Slices per problem from the selector, checked by the residual probe: each
+// product is formed with alpha = 1, beta = 0 in library memory, probed, and
+// redone one slice higher while its estimate misses the target; C is then
+// finished with alpha and beta exactly as the fused epilogue would.
+int auto_batched(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+                 const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A,
+                 const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
+                 const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
+                 int *slices_used) {
+  if (!g_sel.loaded) return OZAKI_ERR_NO_SELECTOR;
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  if (dev != g_sel.dev) return OZAKI_ERR_NO_SELECTOR;
+  hipStream_t st = g.stream;
+  std::vector<int> used((size_t)batch, 0);
+  std::vector<int64_t> E;  // emulated problems
+  std::vector<ScaleOp> scales;
+  for (int64_t b = 0; b < batch; ++b) {
+    if (m[b] == 0 || n[b] == 0) continue;
+    const bool alpha_zero = alpha[b].re == 0.0 && alpha[b].im == 0.0;
+    const bool beta_zero = beta[b].re == 0.0 && beta[b].im == 0.0;
+    const bool beta_one = beta[b].re == 1.0 && beta[b].im == 0.0;
+    if (alpha_zero || k[b] == 0) {
+      if (!beta_one) scales.push_back({m[b], n[b], ldc[b], beta[b].re, beta[b].im, beta_zero, C[b]});
+      continue;
+    }
+    E.push_back(b);
+  }
+  const int64_t ne = (int64_t)E.size();
+  // scratch layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  std::vector<size_t> o_codeA(ne), o_codeB(ne), o_P(ne), o_w(ne), o_est(ne);
+  int64_t sum_m = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t b = E[e];
+    o_codeA[e] = take(sizeof(int) * m[b]);
+    o_codeB[e] = take(sizeof(int) * n[b]);
+    o_P[e] = take(sizeof(ozaki_z) * m[b] * n[b]);
+    o_w[e] = take(probe_workspace_bytes(k[b]));
+    o_est[e] = take(sizeof(double) * m[b]);
+    sum_m += m[b];
+  }
+  const size_t o_hist = take(sizeof(int) * 64 * ne), o_dims = take(sizeof(int64_t) * 3 * ne),
+               o_feat = take(sizeof(float) * 64 * ne), o_y = take(sizeof(float) * ne),
+               o_scan = take(sizeof(ScanTask) * 2 * ne), o_scan_s = take(sizeof(int64_t) * (2 * ne + 1)),
+               o_ft = take(sizeof(FeatTask) * 2 * ne), o_ft_s = take(sizeof(int64_t) * (2 * ne + 1)),
+               o_pt = take(sizeof(ProbeTask) * ne), o_pt_k = take(sizeof(int64_t) * (ne + 1)),
+               o_pt_m = take(sizeof(int64_t) * (ne + 1)), o_ax = take(sizeof(AxpbyTask) * ne),
+               o_ax_s = take(sizeof(int64_t) * (ne + 1)), o_mlp = take(mlp_scratch_bytes(ne));
+  char *ws = nullptr;
+  if ((rc = auto_ws(off, &ws))) return rc;
+
+  // features and selector
+  std::vector<ScanTask> scans;
+  std::vector<FeatTask> feats;
+  std::vector<int64_t> dims;
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t b = E[e];
+    const View va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
+    const View vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
+    int *ca = reinterpret_cast<int *>(ws + o_codeA[e]);
+    int *cb = reinterpret_cast<int *>(ws + o_codeB[e]);
+    int *h = reinterpret_cast<int *>(ws + o_hist) + 64 * e;
+    scans.push_back({va, ca, 1, va.sr == 1 ? 1 : 0});
+    scans.push_back({vb, cb, 1, vb.sr == 1 ? 1 : 0});
+    feats.push_back({va, ca, h, 1, va.sr == 1 ? 1 : 0, 32});
+    feats.push_back({vb, cb, h + 32, 1, vb.sr == 1 ? 1 : 0, 31});
+    dims.push_back(m[b]);
+    dims.push_back(n[b]);
+    dims.push_back(k[b]);
+  }
+  std::vector<int64_t> ss(2 * ne + 1, 0), fs(2 * ne + 1, 0);
+  for (size_t t = 0; t < scans.size(); ++t) ss[t + 1] = ss[t] + scan_task_blocks(scans[t]);
+  for (size_t t = 0; t < feats.size(); ++t) fs[t + 1] = fs[t] + feat_task_blocks(feats[t]);
+  auto h2d = [&](size_t o, const void *src, size_t bytes) {
+    return bytes ? hip_rc(hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st)) : OZAKI_OK;
+  };
+  if ((rc = h2d(o_scan, scans.data(), scans.size() * sizeof(ScanTask)))) return rc;
+  if ((rc = h2d(o_scan_s, ss.data(), ss.size() * sizeof(int64_t)))) return rc;
+  if ((rc = h2d(o_ft, feats.data(), feats.size() * sizeof(FeatTask)))) return rc;
+  if ((rc = h2d(o_ft_s, fs.data(), fs.size() * sizeof(int64_t)))) return rc;
+  if ((rc = h2d(o_dims, dims.data(), dims.size() * sizeof(int64_t)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(reinterpret_cast<int *>(ws + o_hist), 64 * ne, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_scan_batched(reinterpret_cast<const ScanTask *>(ws + o_scan),
+                                       reinterpret_cast<const int64_t *>(ws + o_scan_s),
+                                       (int)scans.size(), ss.back(), st))))
+    return rc;
+  if ((rc = hip_rc(launch_feat_hist(reinterpret_cast<const FeatTask *>(ws + o_ft),
+                                    reinterpret_cast<const int64_t *>(ws + o_ft_s),
+                                    (int)feats.size(), fs.back(), st))))
+    return rc;
+  if ((rc = hip_rc(launch_feat_finish(reinterpret_cast<const int *>(ws + o_hist),
+                                      reinterpret_cast<const int64_t *>(ws + o_dims),
+                                      reinterpret_cast<float *>(ws + o_feat), ne, st))))
+    return rc;
+  if ((rc = hip_rc(mlp_forward(g_sel.state, ne, reinterpret_cast<const float *>(ws + o_feat),
+                               reinterpret_cast<float *>(ws + o_y), ws + o_mlp, st))))
+    return rc;
+  std::vector<float> y(ne);
+  if (ne && (rc = hip_rc(hipMemcpyAsync(y.data(), ws + o_y, sizeof(float) * ne,
+                                        hipMemcpyDeviceToHost, st))))
+    return rc;
+  if ((rc = hip_rc(hipStreamSynchronize(st)))) return rc;
+  std::vector<int> s_of(ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    const double v = std::ceil((double)y[e] + (double)g_sel.margin);
+    s_of[e] = (int)std::min<double>(OZAKI_S_MAX, std::max<double>(1.0, std::isfinite(v) ? v : OZAKI_S_MAX));
+  }
+
+  // emulate, probe, raise
+  std::vector<int64_t> pending(ne);
+  for (int64_t e = 0; e < ne; ++e) pending[e] = e;
+  for (int round = 0; !pending.empty() && round <= OZAKI_S_MAX; ++round) {
+    const size_t np = pending.size();
+    std::vector<char> ta(np), tb(np);
+    std::vector<int64_t> mm(np), nn(np), kk(np), la(np), lb(np), lc(np);
+    std::vector<ozaki_z> one(np, ozaki_z{1.0, 0.0}), zero(np, ozaki_z{0.0, 0.0});
+    std::vector<const ozaki_z *> pa(np), pb(np);
+    std::vector<ozaki_z *> pc(np);
+    std::vector<int> sl(np);
+    std::vector<ProbeTask> pts(np);
+    std::vector<int64_t> sk(np + 1, 0), sm(np + 1, 0);
+    for (size_t x = 0; x < np; ++x) {
+      const int64_t e = pending[x], b = E[e];
+      ta[x] = transa[b];
+      tb[x] = transb[b];
+      mm[x] = m[b];
+      nn[x] = n[b];
+      kk[x] = k[b];
+      la[x] = lda[b];
+      lb[x] = ldb[b];
+      lc[x] = m[b];
+      pa[x] = A[b];
+      pb[x] = B[b];
+      pc[x] = reinterpret_cast<ozaki_z *>(ws + o_P[e]);
+      sl[x] = s_of[e];
+      ProbeTask &pt = pts[x];
+      pt.va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
+      pt.vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
+      pt.C = pc[x];
+      pt.ldc = m[b];
+      pt.cplx = 1;
+      pt.nv = 2;
+      pt.seed = 0x5eed0000ull + (uint64_t)round;
+      pt.w = reinterpret_cast<double *>(ws + o_w[e]);
+      pt.ub = pt.w + (size_t)k[b] * 16;
+      pt.est = reinterpret_cast<double *>(ws + o_est[e]);
+      sk[x + 1] = sk[x] + probe_task_blocks_k(pt);
+      sm[x + 1] = sm[x] + probe_task_blocks_m(pt);
+    }
+    if ((rc = run_fixed_batched(ta.data(), tb.data(), mm.data(), nn.data(), kk.data(), one.data(),
+                                pa.data(), la.data(), pb.data(), lb.data(), zero.data(), pc.data(),
+                                lc.data(), (int64_t)np, sl.data())))
+      return rc;
+    if ((rc = h2d(o_pt, pts.data(), np * sizeof(ProbeTask)))) return rc;
+    if ((rc = h2d(o_pt_k, sk.data(), (np + 1) * sizeof(int64_t)))) return rc;
+    if ((rc = h2d(o_pt_m, sm.data(), (np + 1) * sizeof(int64_t)))) return rc;
+    if ((rc = hip_rc(launch_probe_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt),
+                                          reinterpret_cast<const int64_t *>(ws + o_pt_k), sk.back(),
+                                          reinterpret_cast<const int64_t *>(ws + o_pt_m), sm.back(),
+                                          (int)np, st))))
+      return rc;
+    std::vector<std::vector<double>> est(np);
+    for (size_t x = 0; x < np; ++x) {
+      est[x].resize(mm[x]);
+      if ((rc = hip_rc(hipMemcpyAsync(est[x].data(), ws + o_est[pending[x]], sizeof(double) * mm[x],
+                                      hipMemcpyDeviceToHost, st))))
+        return rc;
+    }
+    if ((rc = hip_rc(hipStreamSynchronize(st)))) return rc;
+    std::vector<int64_t> next;
+    for (size_t x = 0; x < np; ++x) {
+      double mx = 0.0;
+      bool bad = false;
+      for (double v : est[x]) {
+        if (std::isnan(v)) bad = true;  // non-finite inputs: NaN rows, nothing to raise
+        else mx = std::max(mx, v);
+      }
+      const int64_t e = pending[x];
+      if (!bad && mx * g_sel.kappa > g_sel.target && s_of[e] < OZAKI_S_MAX) {
+        ++s_of[e];
+        next.push_back(e);
+      }
+    }
+    pending.swap(next);
+  }
+
+  // finish: C = alpha P + beta C
+  std::vector<AxpbyTask> ax(ne);
+  std::vector<int64_t> as(ne + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t b = E[e];
+    ax[e] = {ws + o_P[e], C[b], m[b], n[b], ldc[b], alpha[b].re, alpha[b].im, beta[b].re, beta[b].im,
+             (beta[b].re == 0.0 && beta[b].im == 0.0) ? 1 : 0};
+    as[e + 1] = as[e] + axpby_task_blocks(ax[e]);
+    used[b] = s_of[e];
+  }
+  if ((rc = h2d(o_ax, ax.data(), ne * sizeof(AxpbyTask)))) return rc;
+  if ((rc = h2d(o_ax_s, as.data(), (ne + 1) * sizeof(int64_t)))) return rc;
+  if ((rc = hip_rc(launch_axpby_batched(reinterpret_cast<const AxpbyTask *>(ws + o_ax),
+                                        reinterpret_cast<const int64_t *>(ws + o_ax_s), (int)ne,
+                                        as.back(), st))))
+    return rc;
+  for (const ScaleOp &sc : scales)
+    if ((rc = hip_rc(launch_scale(true, sc.m, sc.n, sc.br, sc.bi, sc.beta_zero, sc.C, sc.ldc, st))))
+      return rc;
+  if ((rc = hip_rc(hipStreamSynchronize(st)))) return rc;  // host tables above go out of scope
+  if (slices_used != nullptr)
+    for (int64_t b = 0; b < batch; ++b) slices_used[b] = used[b];
+  return OZAKI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -743,11 +1034,10 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
   if (!beta) return -11;
   if (!C) return -12;
   if (!ldc) return -13;
-  if (slices == nullptr) return OZAKI_ERR_NO_SELECTOR;
   for (int64_t b = 0; b < batch; ++b) {
     int rc = check_gemm_args(transa[b], transb[b], m[b], n[b], k[b], lda[b], ldb[b], ldc[b]);
     if (rc) return rc;
-    if (slices[b] < 1 || slices[b] > OZAKI_S_MAX) return -15;
+    if (slices != nullptr && (slices[b] < 1 || slices[b] > OZAKI_S_MAX)) return -15;
     if (m[b] == 0 || n[b] == 0) continue;
     if (C[b] == nullptr) return -12;
     const bool alpha_zero = alpha[b].re == 0.0 && alpha[b].im == 0.0;
@@ -755,16 +1045,18 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
     if (A[b] == nullptr) return -7;
     if (B[b] == nullptr) return -9;
   }
-  BatchedPlan *pl = nullptr;
-  int rc = get_plan(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, slices, &pl);
-  if (rc) return rc;
-  if (pl->exec != nullptr)
-    rc = hip_rc(hipGraphLaunch(pl->exec, g.stream));
-  else
-    rc = enqueue_plan(*pl, g.stream, false);
+  if (slices == nullptr)
+    return auto_batched(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch,
+                        slices_used);
+  int rc = run_fixed_batched(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch,
+                             slices);
   if (rc == OZAKI_OK && slices_used != nullptr)
-    for (int64_t b = 0; b < batch; ++b) slices_used[b] = pl->used[b];
+    for (int64_t b = 0; b < batch; ++b) slices_used[b] = slices[b];
   return rc;
+}
+
+int ozaki_load_selector(const float *params, float margin, double target, double kappa) {
+  return load_selector(params, margin, target, kappa);
 }
 
 int ozaki_batched_graphs(int on) {
@@ -810,6 +1102,102 @@ int ozaki_probe(char kind, char transa, char transb, int64_t m, int64_t n, int64
   const View va = view_opA(A, transa, m, k, lda, cplx);
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
   return hip_rc(launch_probe(va, vb, cplx, C, ldc, m, n, k, nvec, seed, wsv, est, g.stream));
+}
+
+int ozaki_features(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                   const void *A, int64_t lda, const void *B, int64_t ldb, float *feat) {
+  kind = up(kind);
+  if (kind != 'D' && kind != 'Z') return -1;
+  const bool cplx = kind == 'Z';
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, std::max<int64_t>(1, m));
+  if (rc) {
+    switch (rc) {
+      case -8: return -8;
+      case -10: return -10;
+      default: return rc - 1;
+    }
+  }
+  if (m == 0 || n == 0 || k == 0) return -4 - (m == 0 ? 0 : (n == 0 ? 1 : 2));
+  if (feat == nullptr) return -11;
+  if (A == nullptr) return -7;
+  if (B == nullptr) return -9;
+  // workspace: codes (m + n), histogram (64), dims (3), task tables
+  const size_t oc = 0, ocb = align256(sizeof(int) * m), oh = ocb + align256(sizeof(int) * n),
+               od = oh + 256, ot = od + 256, os = ot + align256(2 * sizeof(FeatTask)),
+               total = os + 256;
+  void *wsv = nullptr;
+  if ((rc = get_workspace(total, &wsv))) return rc;
+  char *ws = static_cast<char *>(wsv);
+  int *codeA = reinterpret_cast<int *>(ws + oc);
+  int *codeB = reinterpret_cast<int *>(ws + ocb);
+  int *hist = reinterpret_cast<int *>(ws + oh);
+  const View va = view_opA(A, transa, m, k, lda, cplx);
+  const View vb = view_opB(B, transb, k, n, ldb, cplx);
+  FeatTask tk[2] = {{va, codeA, hist, cplx ? 1 : 0, va.sr == 1 ? 1 : 0, 32},
+                    {vb, codeB, hist + 32, cplx ? 1 : 0, vb.sr == 1 ? 1 : 0, 31}};
+  int64_t start[3] = {0, feat_task_blocks(tk[0]), 0};
+  start[2] = start[1] + feat_task_blocks(tk[1]);
+  const int64_t dims[3] = {m, n, k};
+  hipStream_t st = g.stream;
+  if ((rc = hip_rc(hipMemcpyAsync(ws + od, dims, sizeof(dims), hipMemcpyHostToDevice, st)))) return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(ws + ot, tk, sizeof(tk), hipMemcpyHostToDevice, st)))) return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(ws + os, start, sizeof(start), hipMemcpyHostToDevice, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(codeA, m, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(codeB, n, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(hist, 64, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(va, cplx, codeA, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(vb, cplx, codeB, st)))) return rc;
+  if ((rc = hip_rc(launch_feat_hist(reinterpret_cast<const FeatTask *>(ws + ot),
+                                    reinterpret_cast<const int64_t *>(ws + os), 2, start[2], st))))
+    return rc;
+  rc = hip_rc(launch_feat_finish(hist, reinterpret_cast<const int64_t *>(ws + od), feat, 1, st));
+  if (rc == OZAKI_OK) rc = hip_rc(hipStreamSynchronize(st));  // host arrays above go out of scope
+  return rc;
+}
+
+size_t ozaki_mlp_state_bytes(void) { return mlp_state_bytes(); }
+size_t ozaki_mlp_scratch_bytes(int64_t batch) { return batch < 0 ? 0 : mlp_scratch_bytes(batch); }
+
+int ozaki_mlp_init(void *state, uint64_t seed) {
+  if (state == nullptr) return -1;
+  return hip_rc(mlp_init(state, seed, g.stream));
+}
+
+int ozaki_mlp_refresh(void *state) {
+  if (state == nullptr) return -1;
+  return hip_rc(mlp_refresh(state, g.stream));
+}
+
+int ozaki_mlp_forward(const void *state, int64_t batch, const float *X, float *y, void *scratch) {
+  if (state == nullptr) return -1;
+  if (batch < 0) return -2;
+  if (batch == 0) return OZAKI_OK;
+  if (X == nullptr) return -3;
+  if (y == nullptr) return -4;
+  if (scratch == nullptr) return -5;
+  return hip_rc(mlp_forward(state, batch, X, y, scratch, g.stream));
+}
+
+int ozaki_mlp_backward(void *state, int64_t batch, const float *y, const float *target,
+                       float under_weight, float *loss, void *scratch) {
+  if (state == nullptr) return -1;
+  if (batch < 0) return -2;
+  if (batch == 0) return OZAKI_OK;
+  if (y == nullptr) return -3;
+  if (target == nullptr) return -4;
+  if (!(under_weight > 0.0f)) return -5;
+  if (scratch == nullptr) return -7;
+  return hip_rc(mlp_backward(state, batch, y, target, under_weight, loss, scratch, g.stream));
+}
+
+int ozaki_mlp_adam(void *state, float lr, float beta1, float beta2, float eps, int64_t step) {
+  if (state == nullptr) return -1;
+  if (!(lr > 0.0f)) return -2;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f)) return -3;
+  if (!(beta2 >= 0.0f && beta2 < 1.0f)) return -4;
+  if (!(eps > 0.0f)) return -5;
+  if (step < 1) return -6;
+  return hip_rc(mlp_adam(state, lr, beta1, beta2, eps, step, g.stream));
 }
 
 int ozaki_set_stream(void *hip_stream) {

@@ -98,7 +98,60 @@ int gemm_num_configs();
 size_t gemm_flush_bytes(int S, int cfg, int num_cu);
 hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
 
-// Randomized residual probe (see ozaki_probe.hip).
+// Selector features and MLP (see ozaki_selector.hip).
+struct FeatTask {
+  View v;
+  const int *code;
+  int *hist;  // nbins integer counts of this operand side
+  int cplx;
+  int rows_fast;
+  int nbins;  // 32 for op(A) rows, 31 for op(B) columns
+};
+int64_t feat_task_blocks(const FeatTask &t);
+hipError_t launch_feat_hist(const FeatTask *tasks, const int64_t *start, int ntasks, int64_t nblocks,
+                            hipStream_t st);
+// dims[3p..3p+2] = m, n, k of problem p; hist[64p..] holds A bins 0..31 and B
+// bins 32..62.
+hipError_t launch_feat_finish(const int *hist, const int64_t *dims, float *feat, int64_t np,
+                              hipStream_t st);
+int64_t mlp_params();
+size_t mlp_state_bytes();
+size_t mlp_scratch_bytes(int64_t batch);
+hipError_t mlp_init(void *state, uint64_t seed, hipStream_t st);
+hipError_t mlp_refresh(void *state, hipStream_t st);
+hipError_t mlp_forward(const void *state, int64_t b, const float *X, float *y, void *scratch,
+                       hipStream_t st);
+hipError_t mlp_backward(void *state, int64_t b, const float *y, const float *target, float under,
+                        float *loss, void *scratch, hipStream_t st);
+hipError_t mlp_adam(void *state, float lr, float b1, float b2, float eps, int64_t step,
+                    hipStream_t st);
+
+// Randomized residual probe (see ozaki_probe.hip). A batched task probes one
+// product: w and ub are its scratch (k * 17 doubles), est receives m values.
+struct ProbeTask {
+  View va, vb;
+  const void *C;
+  int64_t ldc;
+  int cplx;
+  int nv;
+  uint64_t seed;
+  double *w, *ub, *est;
+};
+// C = alpha P + beta C over complex problems (P: m x n, leading dimension m).
+struct AxpbyTask {
+  const void *P;
+  void *C;
+  int64_t m, n, ldc;
+  double ar, ai, br, bi;
+  int beta_zero;
+};
+int64_t probe_task_blocks_k(const ProbeTask &t);
+int64_t probe_task_blocks_m(const ProbeTask &t);
+int64_t axpby_task_blocks(const AxpbyTask &t);
+hipError_t launch_probe_batched(const ProbeTask *tasks, const int64_t *start_k, int64_t nblk_k,
+                                const int64_t *start_m, int64_t nblk_m, int ntasks, hipStream_t st);
+hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, int ntasks,
+                                int64_t nblocks, hipStream_t st);
 size_t probe_workspace_bytes(int64_t k);
 int probe_max_vectors();
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,

@@ -78,9 +78,7 @@ __device__ __forceinline__ double2 ld(const View &v, int64_t r, int64_t l) {
 // per l. vb views op(B) with rows = columns j and contraction = l, so
 // op(B)(l, j) = vb(j, l). Output per l: [v][re.hi, re.lo, im.hi, im.lo].
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_probe_bx(View vb, int nv, uint64_t seed, double *w,
-                                                  double *ub) {
-  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ void probe_bx(const View &vb, int nv, uint64_t seed, double *w, double *ub, int64_t l) {
   const int64_t K = vb.L, N = vb.R;
   if (l >= K) return;
   Dd re[kMaxVec], im[kMaxVec];
@@ -104,13 +102,18 @@ __global__ void __launch_bounds__(256) k_probe_bx(View vb, int nv, uint64_t seed
   ub[l] = u;
 }
 
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_probe_bx(View vb, int nv, uint64_t seed, double *w,
+                                                  double *ub) {
+  probe_bx<CPLX>(vb, nv, seed, w, ub, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
 // Per row i: z_v = sum_l op(A)(i, l) w_v[l] (w as hi + lo), y_v = sum_j C(i, j)
 // x_v[j], u = sum_l |op(A)(i, l)| ub[l]; est[i] as described above.
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_probe_rows(View va, const void *C, int64_t ldc, int64_t n,
-                                                    int nv, uint64_t seed, const double *w,
-                                                    const double *ub, double *est) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ void probe_rows(const View &va, const void *C, int64_t ldc, int64_t n, int nv,
+                           uint64_t seed, const double *w, const double *ub, double *est,
+                           int64_t i) {
   const int64_t M = va.R, K = va.L;
   if (i >= M) return;
   Dd zr[kMaxVec], zi[kMaxVec], yr[kMaxVec], yi[kMaxVec];
@@ -168,7 +171,95 @@ __global__ void __launch_bounds__(256) k_probe_rows(View va, const void *C, int6
   est[i] = e;
 }
 
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_probe_rows(View va, const void *C, int64_t ldc, int64_t n,
+                                                    int nv, uint64_t seed, const double *w,
+                                                    const double *ub, double *est) {
+  probe_rows<CPLX>(va, C, ldc, n, nv, seed, w, ub, est, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+__device__ __forceinline__ int find_task3(const int64_t *start, int ntasks, int64_t b) {
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Batched forms: task t owns blocks start[t] .. start[t+1]-1 (k / 256 blocks
+// for the first kernel, m / 256 for the second).
+__global__ void __launch_bounds__(256) k_probe_bx_batched(const ProbeTask *tasks,
+                                                          const int64_t *start, int ntasks) {
+  const int t = find_task3(start, ntasks, blockIdx.x);
+  const ProbeTask tk = tasks[t];
+  const int64_t l = (blockIdx.x - start[t]) * 256 + threadIdx.x;
+  if (tk.cplx)
+    probe_bx<true>(tk.vb, tk.nv, tk.seed, tk.w, tk.ub, l);
+  else
+    probe_bx<false>(tk.vb, tk.nv, tk.seed, tk.w, tk.ub, l);
+}
+
+__global__ void __launch_bounds__(256) k_probe_rows_batched(const ProbeTask *tasks,
+                                                            const int64_t *start, int ntasks) {
+  const int t = find_task3(start, ntasks, blockIdx.x);
+  const ProbeTask tk = tasks[t];
+  const int64_t i = (blockIdx.x - start[t]) * 256 + threadIdx.x;
+  if (tk.cplx)
+    probe_rows<true>(tk.va, tk.C, tk.ldc, tk.vb.R, tk.nv, tk.seed, tk.w, tk.ub, tk.est, i);
+  else
+    probe_rows<false>(tk.va, tk.C, tk.ldc, tk.vb.R, tk.nv, tk.seed, tk.w, tk.ub, tk.est, i);
+}
+
+// C_p = alpha_p P_p + beta_p C_p for complex problems, the epilogue formula of
+// the fused GEMM (every product and sum rounded on its own); one thread per
+// entry, task t owns blocks start[t] ..
+__global__ void __launch_bounds__(256) k_axpby_batched(const AxpbyTask *tasks, const int64_t *start,
+                                                       int ntasks) {
+  const int t = find_task3(start, ntasks, blockIdx.x);
+  const AxpbyTask tk = tasks[t];
+  const int64_t idx = (blockIdx.x - start[t]) * 256 + threadIdx.x;
+  if (idx >= tk.m * tk.n) return;
+  const int64_t i = idx % tk.m, j = idx / tk.m;
+  const double2 p = reinterpret_cast<const double2 *>(tk.P)[i + j * tk.m];
+  double2 *cp = reinterpret_cast<double2 *>(tk.C) + i + j * tk.ldc;
+  double re = sub_rn(mul_rn(tk.ar, p.x), mul_rn(tk.ai, p.y));
+  double im = add_rn(mul_rn(tk.ar, p.y), mul_rn(tk.ai, p.x));
+  if (!tk.beta_zero) {
+    const double2 z = *cp;
+    re = add_rn(re, sub_rn(mul_rn(tk.br, z.x), mul_rn(tk.bi, z.y)));
+    im = add_rn(im, add_rn(mul_rn(tk.br, z.y), mul_rn(tk.bi, z.x)));
+  }
+  *cp = make_double2(re, im);
+}
+
 }  // namespace
+
+int64_t probe_task_blocks_k(const ProbeTask &t) { return (t.vb.L + 255) / 256; }
+int64_t probe_task_blocks_m(const ProbeTask &t) { return (t.va.R + 255) / 256; }
+int64_t axpby_task_blocks(const AxpbyTask &t) { return (t.m * t.n + 255) / 256; }
+
+hipError_t launch_probe_batched(const ProbeTask *tasks, const int64_t *start_k, int64_t nblk_k,
+                                const int64_t *start_m, int64_t nblk_m, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  if (nblk_k > 0)
+    hipLaunchKernelGGL(k_probe_bx_batched, dim3((unsigned)nblk_k), dim3(256), 0, st, tasks, start_k,
+                       ntasks);
+  if (nblk_m > 0)
+    hipLaunchKernelGGL(k_probe_rows_batched, dim3((unsigned)nblk_m), dim3(256), 0, st, tasks,
+                       start_m, ntasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, int ntasks,
+                                int64_t nblocks, hipStream_t st) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby_batched, dim3((unsigned)nblocks), dim3(256), 0, st, tasks, start, ntasks);
+  return hipGetLastError();
+}
 
 size_t probe_workspace_bytes(int64_t k) { return (size_t)k * (kMaxVec * 4 + 1) * sizeof(double) + 256; }
 int probe_max_vectors() { return kMaxVec; }

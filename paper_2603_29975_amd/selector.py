@@ -1,0 +1,262 @@
+"""Training and evaluation of the learned slice-count selector.
+
+Data come from the emulator itself: for each generated (A, B) pair the GPU
+forms the emulated product at every slice count s = S_LO..12 (the batched
+entry point) and the native FP64 matrix-core product as the reference; the
+label is the smallest s whose componentwise error max |C_s - C_ref| /
+(|A||B|) reaches the target (|A||B| is formed by the native kernel too). The
+features are the library's (ozaki_features). Training runs the library's BF16
+MLP kernels (forward, backward, Adam); PyTorch only holds device buffers and
+does the elementwise bookkeeping of the labels (differences, ratios, maxima).
+
+The paper tunes the emulation precision by hand per run (Sections 3.2 and 4:
+mantissa bits 31..63, moduli 10..18) and notes that accuracy depends on the
+operator as well as the precision; the selector makes that choice per product.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import (MLP_PARAMS, OzakiError, ozaki_features, ozaki_mlp_adam, ozaki_mlp_backward,
+               ozaki_mlp_forward, ozaki_mlp_init, ozaki_mlp_scratch_bytes, ozaki_mlp_state_bytes,
+               ozaki_native_dgemm, ozaki_native_zgemm, ozaki_zgemm_batched)
+
+S_LO = 3
+S_HI = 12
+
+
+def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32):
+    """m, n from mn_choices; k = 32 j with P(j) ~ 1/j (the batched law)."""
+    j = np.arange(1, kmax_j + 1)
+    p = (1.0 / j) / np.sum(1.0 / j)
+    m = rng.choice(mn_choices, count)
+    n = rng.choice(mn_choices, count)
+    k = rng.choice(j, count, p=p) * 32
+    return m.astype(np.int64), n.astype(np.int64), k.astype(np.int64)
+
+
+def generate_pairs(count: int, seed: int, mn_choices=(32, 64)):
+    """Complex (A, B) pairs from four families: per-entry binade spread,
+    per-matrix exponent spread with row/column scaling, Gaussian with
+    power-of-two row/column scaling, and KKR-shaped blocks."""
+    from workloads import batched_problems, complex_normal, kkr_operands
+    rng = np.random.default_rng(seed)
+    ms, ns, ks = pair_sizes(rng, count, mn_choices)
+    fam = rng.integers(0, 4, count)
+    pairs = []
+    for i in range(count):
+        m, n, k = int(ms[i]), int(ns[i]), int(ks[i])
+        f = fam[i]
+        sub = int(rng.integers(0, 2 ** 31))
+        if f == 0:
+            w = int(rng.integers(0, 13))
+            r = np.random.default_rng(sub)
+            A = (r.uniform(-1, 1, (m, k)) + 1j * r.uniform(-1, 1, (m, k))) * np.ldexp(1.0, r.integers(-w, w + 1, (m, k)))
+            B = (r.uniform(-1, 1, (k, n)) + 1j * r.uniform(-1, 1, (k, n))) * np.ldexp(1.0, r.integers(-w, w + 1, (k, n)))
+        elif f == 1:
+            (A, B), = batched_problems(1, sub, sizes=([m], [n], [k]))[0]
+        elif f == 2:
+            r = np.random.default_rng(sub)
+            A = complex_normal(r, (m, k)) * np.ldexp(1.0, r.integers(-30, 31, m))[:, None]
+            B = complex_normal(r, (k, n)) * np.ldexp(1.0, r.integers(-30, 31, n))[None, :]
+        else:
+            nb = max(1, k // 32)
+            A_full, B_full = kkr_operands(nb, seed=sub, n_rhs=n)
+            A = np.ascontiguousarray(A_full[:m, :])
+            B = B_full
+            k = A.shape[1]
+        pairs.append((np.ascontiguousarray(A, dtype=np.complex128),
+                      np.ascontiguousarray(B, dtype=np.complex128)))
+    return pairs
+
+
+class DeviceBatch:
+    """Column-major device copies of a list of complex pairs in flat buffers."""
+
+    def __init__(self, pairs):
+        import torch
+        self.pairs = pairs
+        self.m = np.array([A.shape[0] for A, _ in pairs], dtype=np.int64)
+        self.k = np.array([A.shape[1] for A, _ in pairs], dtype=np.int64)
+        self.n = np.array([B.shape[1] for _, B in pairs], dtype=np.int64)
+        sa, sb, sc = self.m * self.k, self.k * self.n, self.m * self.n
+        self.oa = np.concatenate([[0], np.cumsum(sa)])
+        self.ob = np.concatenate([[0], np.cumsum(sb)])
+        self.oc = np.concatenate([[0], np.cumsum(sc)])
+        ha = np.concatenate([A.T.ravel() for A, _ in pairs])
+        hb = np.concatenate([B.T.ravel() for _, B in pairs])
+        self.A = torch.from_numpy(ha).cuda()
+        self.B = torch.from_numpy(hb).cuda()
+        self.Aabs = self.A.abs()
+        self.Babs = self.B.abs()
+        self.nc = int(self.oc[-1])
+        self.seg = torch.from_numpy(np.repeat(np.arange(len(pairs)), sc)).cuda()
+
+    def ptrs(self, t, off, elem):
+        base = t.data_ptr()
+        return [base + int(o) * elem for o in off[:-1]]
+
+
+def label_pairs(pairs, target: float, s_lo: int = S_LO, s_hi: int = S_HI, chunk: int = 2048):
+    """Smallest s in [s_lo, s_hi] with componentwise error <= target for each
+    pair (s_hi + 1 when none reaches it), and the error table err[pair, s]."""
+    import torch
+    labels = np.zeros(len(pairs), dtype=np.int64)
+    errs = np.zeros((len(pairs), s_hi - s_lo + 1))
+    for c0 in range(0, len(pairs), chunk):
+        sub = pairs[c0:c0 + chunk]
+        db = DeviceBatch(sub)
+        nb = len(sub)
+        ref = torch.zeros(db.nc, dtype=torch.complex128, device="cuda")
+        den = torch.zeros(db.nc, dtype=torch.float64, device="cuda")
+        pa, pb = db.ptrs(db.A, db.oa, 16), db.ptrs(db.B, db.ob, 16)
+        paa, pba = db.ptrs(db.Aabs, db.oa, 8), db.ptrs(db.Babs, db.ob, 8)
+        pr, pd = db.ptrs(ref, db.oc, 16), db.ptrs(den, db.oc, 8)
+        for b in range(nb):
+            m, n, k = int(db.m[b]), int(db.n[b]), int(db.k[b])
+            rc = ozaki_native_zgemm("N", "N", m, n, k, 1.0, pa[b], m, pb[b], k, 0.0, pr[b], m)
+            rc |= ozaki_native_dgemm("N", "N", m, n, k, 1.0, paa[b], m, pba[b], k, 0.0, pd[b], m)
+            if rc:
+                raise OzakiError(rc, "native reference")
+        out = torch.zeros(db.nc, dtype=torch.complex128, device="cuda")
+        po = db.ptrs(out, db.oc, 16)
+        big = torch.full((nb,), 0.0, dtype=torch.float64, device="cuda")
+        for s in range(s_lo, s_hi + 1):
+            rc = ozaki_zgemm_batched(["N"] * nb, ["N"] * nb, db.m, db.n, db.k, [1.0] * nb, pa,
+                                     db.m, pb, db.k, [0.0] * nb, po, db.m, nb, [s] * nb)
+            if rc:
+                raise OzakiError(rc, "ozaki_zgemm_batched")
+            ratio = (out - ref).abs() / den
+            ratio = torch.where(den > 0, ratio, torch.where((out - ref).abs() > 0,
+                                                              torch.full_like(ratio, math.inf),
+                                                              torch.zeros_like(ratio)))
+            e = big.clone().scatter_reduce_(0, db.seg, ratio, reduce="amax", include_self=True)
+            errs[c0:c0 + nb, s - s_lo] = e.cpu().numpy()
+        ok = errs[c0:c0 + nb] <= target
+        first = np.where(ok.any(axis=1), ok.argmax(axis=1) + s_lo, s_hi + 1)
+        labels[c0:c0 + nb] = first
+    return labels, errs
+
+
+def features_of(pairs):
+    import torch
+    feats = torch.zeros((len(pairs), 64), dtype=torch.float32, device="cuda")
+    for i, (A, B) in enumerate(pairs):
+        m, k = A.shape
+        n = B.shape[1]
+        Ad = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+        Bd = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
+        rc = ozaki_features("z", "N", "N", m, n, k, Ad, m, Bd, k, feats[i])
+        if rc:
+            raise OzakiError(rc, "ozaki_features")
+    return feats
+
+
+def train(feats, labels, epochs=20, batch=256, lr=1e-3, under=4.0, seed=1005, log=None):
+    """Adam on the asymmetric squared loss; returns the FP32 parameters."""
+    import torch
+    n = feats.shape[0]
+    y_t = torch.from_numpy(np.asarray(labels, dtype=np.float32)).cuda()
+    state = torch.zeros(ozaki_mlp_state_bytes() // 4 + 16, dtype=torch.float32, device="cuda")
+    if ozaki_mlp_init(state, seed):
+        raise RuntimeError("mlp init")
+    scratch = torch.zeros(ozaki_mlp_scratch_bytes(batch) // 4 + 64, dtype=torch.float32, device="cuda")
+    out = torch.zeros(batch, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed)
+    step = 0
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        tot = 0.0
+        nb = 0
+        for s0 in range(0, n - batch + 1, batch):
+            idx = perm[s0:s0 + batch]
+            X = feats[idx].contiguous()
+            t = y_t[idx].contiguous()
+            step += 1
+            rc = ozaki_mlp_forward(state, batch, X, out, scratch)
+            rc |= ozaki_mlp_backward(state, batch, out, t, under, loss, scratch)
+            rc |= ozaki_mlp_adam(state, lr, 0.9, 0.999, 1e-8, step)
+            if rc:
+                raise RuntimeError("mlp step failed")
+            if s0 % (batch * 64) == 0:
+                tot += loss.item()
+                nb += 1
+        if log:
+            log(f"epoch {ep}: loss {tot / max(nb, 1):.4f}")
+    return state[:MLP_PARAMS].cpu().numpy().copy()
+
+
+def predict(theta, feats):
+    import torch
+    n = feats.shape[0]
+    state = torch.zeros(ozaki_mlp_state_bytes() // 4 + 16, dtype=torch.float32, device="cuda")
+    state[:MLP_PARAMS] = torch.from_numpy(np.asarray(theta, dtype=np.float32)).cuda()
+    from . import ozaki_mlp_refresh
+    ozaki_mlp_refresh(state)
+    scratch = torch.zeros(ozaki_mlp_scratch_bytes(n) // 4 + 64, dtype=torch.float32, device="cuda")
+    out = torch.zeros(n, dtype=torch.float32, device="cuda")
+    if ozaki_mlp_forward(state, n, feats.contiguous(), out, scratch):
+        raise RuntimeError("mlp forward")
+    return out.cpu().numpy()
+
+
+def calibrate_margin(pred, labels, coverage=0.99):
+    """Smallest margin (multiple of 0.05 in [-2, 6]) with ceil(pred + margin) >=
+    label for at least `coverage` of the pairs."""
+    for mg in np.arange(-2.0, 6.0001, 0.05):
+        s = np.clip(np.ceil(pred + mg), 1, S_HI)
+        if np.mean(s >= np.minimum(labels, S_HI)) >= coverage:
+            return float(mg)
+    return 6.0
+
+
+def save(path, theta, margin, target, meta):
+    np.savez(path, theta=np.asarray(theta, dtype=np.float32), margin=np.float32(margin),
+             target=np.float64(target), **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load(path):
+    z = np.load(path, allow_pickle=False)
+    return z["theta"], float(z["margin"]), float(z["target"])
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="train the slice-count selector on the GPU")
+    ap.add_argument("--pairs", type=int, default=200_000)
+    ap.add_argument("--target", type=float, default=1e-11)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--seed", type=int, default=1005)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+
+    def log(*a):
+        print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
+
+    ntrain = int(args.pairs * 0.9)
+    log(f"generating {args.pairs} pairs")
+    pairs = generate_pairs(args.pairs, args.seed)
+    log("labelling")
+    labels, _ = label_pairs(pairs, args.target)
+    log(f"label histogram {np.bincount(labels, minlength=S_HI + 2)[S_LO:]}")
+    feats = features_of(pairs)
+    log("training")
+    theta = train(feats[:ntrain], labels[:ntrain], epochs=args.epochs, seed=args.seed, log=log)
+    pred = predict(theta, feats[ntrain:])
+    margin = calibrate_margin(pred, labels[ntrain:])
+    s_val = np.clip(np.ceil(pred + margin), 1, S_HI)
+    log(f"validation: margin {margin:.2f}, coverage {np.mean(s_val >= np.minimum(labels[ntrain:], S_HI)):.4f}, "
+        f"mean predicted s {s_val.mean():.3f}, mean label {labels[ntrain:].mean():.3f}")
+    save(args.out, theta, margin, args.target,
+         {"pairs": args.pairs, "seed": args.seed, "val_coverage": np.mean(s_val >= np.minimum(labels[ntrain:], S_HI)),
+          "val_mean_s": s_val.mean(), "val_mean_label": labels[ntrain:].mean()})
+    log(f"saved {args.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -149,3 +149,56 @@ def test_batched_full_size_sampled_problems():
         ref = bt.reference(b)
         assert bits_equal(got[b], ref), f"problem {b} ({ms[b]}x{ns[b]}x{ks[b]})"
     _say("batched 512: checked", pick)
+
+
+def _const_selector(value):
+    from oracle import selector as sel
+    theta = np.zeros(sel.P, dtype=np.float32)
+    theta[sel.OFFS["b3"][0]] = value
+    return theta
+
+
+def test_automatic_slices_probe_raises_and_matches_fixed_model():
+    # A selector that always predicts 3 slices: the residual probe must raise
+    # every problem until its estimate meets the target; the result must equal
+    # the model at the final slice count bit for bit.
+    from oracle import dd, metrics
+    bt = _small_batch(seed=21, count=12)
+    bt.slices = None
+    target = 1e-11
+    assert oz.ozaki_load_selector(_const_selector(3.0), 0.0, target, 8.0) == 0
+    nb = len(bt.probs)
+    ms = [A.shape[0] for A, _ in bt.probs]
+    ns = [B.shape[1] for _, B in bt.probs]
+    ks = [A.shape[1] for A, _ in bt.probs]
+    used = []
+    bt.reset_c()
+    rc = oz.ozaki_zgemm_batched([t[0] for t in bt.trans], [t[1] for t in bt.trans], ms, ns, ks,
+                                bt.alphas, bt.Ad, bt.lda, bt.Bd, bt.ldb, bt.betas, bt.Cd, bt.ldc, nb,
+                                None, used)
+    assert rc == 0, oz.ozaki_status_string(rc)
+    _say("automatic slices used", used)
+    assert min(used) >= 3 and max(used) > 3
+    for b in range(nb):
+        got = host(bt.Cd[b], ms[b], ns[b])
+        A, B = bt.probs[b]
+        ref = ozaki.ozaki_gemm("N", "N", A, B, used[b], bt.alphas[b], bt.betas[b], bt.C0s[b])
+        assert bits_equal(got, ref), f"problem {b}"
+        if used[b] < 12 and bt.alphas[b] == 1.0 and bt.betas[b] == 0.0:
+            hi, lo = dd.dd_gemm("N", "N", A, B)
+            err = metrics.err_comp(got, hi, lo, metrics.abs_product("N", "N", A, B))
+            assert err <= 10 * target, (b, used[b], err)
+
+
+def test_automatic_slices_constant_twelve():
+    bt = _small_batch(seed=22, count=6)
+    assert oz.ozaki_load_selector(_const_selector(12.0), 0.5, 1e-11, 8.0) == 0
+    nb = len(bt.probs)
+    ms = [A.shape[0] for A, _ in bt.probs]
+    ns = [B.shape[1] for _, B in bt.probs]
+    ks = [A.shape[1] for A, _ in bt.probs]
+    used = []
+    rc = oz.ozaki_zgemm_batched([t[0] for t in bt.trans], [t[1] for t in bt.trans], ms, ns, ks,
+                                bt.alphas, bt.Ad, bt.lda, bt.Bd, bt.ldb, bt.betas, bt.Cd, bt.ldc, nb,
+                                None, used)
+    assert rc == 0 and used == [12] * nb

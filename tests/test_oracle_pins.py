@@ -502,3 +502,51 @@ def test_probe_invariant_under_row_scaling_and_tracks_error():
     assert true / 30 < est.max() < true * 3
     C7 = ozaki.ozaki_gemm("N", "N", A, B, 7)
     assert probe_est("N", "N", A, B, C7, 2, seed=5).max() < est.max() / 1e4
+
+
+# ------------------------------------------------------------ selector features and MLP
+def test_features_hand_counted_histogram():
+    from oracle.selector import features
+    # rows of A: [1, 0.5, 0] (row exponent 1: deltas 0, 1, zero) and
+    # [0.25, 0.25, 2^-40] (row exponent -1: deltas 0, 0, 38 -> clipped to 30)
+    A = np.array([[1.0, 0.5, 0.0], [0.25, 0.25, 2.0 ** -40]])
+    # columns of B: [3, 1, 0.75] (exp 2: deltas 0, 1, 2) and [0, 0, -2^-3] (exp -2: zero, zero, 0)
+    B = np.array([[3.0, 0.0], [1.0, 0.0], [0.75, -0.125]])
+    f = features("N", "N", A, B)
+    want = np.zeros(64, dtype=np.float32)
+    want[0], want[1], want[30], want[31] = 3 / 6, 1 / 6, 1 / 6, 1 / 6
+    want[32 + 0], want[32 + 1], want[32 + 2], want[32 + 30] = 2 / 6, 1 / 6, 1 / 6, 2 / 6
+    want[63] = np.float32(np.log2(3.0) / 16)
+    assert np.allclose(f, want, rtol=0, atol=1e-7)
+    # complex entries use the larger of the two exponents
+    fz = features("N", "N", A * (1 + 0j) + 1j * np.array([[0, 0, 0], [1.0, 0, 0]]), B + 0j)
+    assert fz[0] == np.float32(2 / 6) and fz[1] == np.float32(1 / 6) and fz[2] == np.float32(1 / 6)
+
+
+def test_mlp_backward_matches_finite_differences():
+    from oracle import selector as sel
+    rng = np.random.default_rng(80)
+    theta = rng.standard_normal(sel.P) * 0.1
+    X = rng.uniform(0, 1, (12, 64))
+    t = rng.uniform(3, 9, 12)
+    g, L = sel.backward(theta, X, t, 4.0, quantize=False)
+    idx = list(rng.choice(sel.P, 40, replace=False)) + [sel.P - 1, sel.OFFS["b1"][0] + 3]
+    for i in idx:
+        h = 1e-6
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (sel.loss(sel.forward(tp, X, False)[0], t, 4.0) - sel.loss(sel.forward(tm, X, False)[0], t, 4.0)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_bf16_rounding_and_adam_first_step():
+    from oracle import selector as sel
+    # bf16 keeps 8 significant bits, rounds to nearest even
+    assert sel.bf16(1.0 + 2 ** -8) == 1.0                   # tie -> even
+    assert sel.bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6     # tie -> even (up)
+    assert sel.bf16(1.0 + 2 ** -7) == 1.0 + 2 ** -7
+    # first Adam step from zero moments: theta - lr * g / (|g| + eps)
+    g = np.array([0.5, -2.0, 0.0, 1e-3])
+    th, m, v = sel.adam(np.zeros(4), np.zeros(4), np.zeros(4), g, 0.01, 0.9, 0.999, 1e-8, 1)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
