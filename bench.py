@@ -91,7 +91,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--slices", type=int, default=7)
     ap.add_argument("--workload", default="kkr2048",
-                    choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512"])
+                    choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512",
+                             "selector512"])
+    ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2603_29975_amd",
+                                                         "selector_weights.npz"),
+                    help="trained selector weights (selector512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (timing and accuracy check)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -117,6 +121,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "batched512":
         return run_batched(args)
+    if args.workload == "selector512":
+        return run_selector(args)
 
     wl = workload(args.workload)
     A, B = wl["A"], wl["B"]
@@ -338,6 +344,29 @@ def run_batched(args):
         "roofline": roofline, "cpu_baseline": cpu,
         "eager_ms_per_step": round(eager_ms, 4), "graph_ms_per_step": round(graph_ms, 4),
         "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_selector(args):
+    """Learned slice selection (+ residual probe) against the best fixed slice
+    count on the 512-problem batch, at a componentwise target of 1e-11."""
+    from paper_2603_29975_amd import selector
+    theta, margin, target = selector.load(args.selector)
+    res = selector.evaluate_gain(theta, margin, target, steps=args.steps, log=log)
+    flops = None
+    from workloads import batched_problems
+    import numpy as np
+    _, (ms, ns, ks) = batched_problems(512, 1003)
+    flops = float(np.sum(8.0 * ms * ns * ks))
+    out = {
+        "metric": METRIC, "value": round(flops / (res["ms_learned"] * 1e-3) / 1e12, 3),
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(res["ms_learned"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "batched_zgemm_512_learned_slices", "target_err_comp": target,
+                   "selector": os.path.basename(args.selector), "margin": margin, "seed": 1003},
+        "roofline": None, "cpu_baseline": None, "selector": res,
     }
     print(json.dumps(out), flush=True)
 

@@ -38,11 +38,33 @@ def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32):
     return m.astype(np.int64), n.astype(np.int64), k.astype(np.int64)
 
 
+def kkr_rows(m, n, k, seed, block=32):
+    """The first m rows of a KKR-shaped A = I - T G (k x k, blocks of 32: T
+    block diagonal with entries of magnitude 10^U[-3,0] and uniform phase, G
+    complex Gaussian decaying as 1 / (1 + block distance)) and a complex
+    Gaussian B (k x n); only the needed block rows are drawn."""
+    from workloads import complex_normal
+    rng = np.random.default_rng(seed)
+    rows = -(-m // block) * block
+    G = complex_normal(rng, (rows, k))
+    bi = np.arange(rows) // block
+    bj = np.arange(k) // block
+    G = G / (1.0 + np.abs(bi[:, None] - bj[None, :]))
+    A = np.zeros((rows, k), dtype=np.complex128)
+    A[np.arange(min(rows, k)), np.arange(min(rows, k))] = 1.0
+    for I in range(rows // block):
+        T = 10.0 ** rng.uniform(-3, 0, (block, block)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (block, block)))
+        sl = slice(I * block, (I + 1) * block)
+        A[sl] -= T @ G[sl]
+    B = complex_normal(rng, (k, n))
+    return A[:m], B
+
+
 def generate_pairs(count: int, seed: int, mn_choices=(32, 64)):
     """Complex (A, B) pairs from four families: per-entry binade spread,
     per-matrix exponent spread with row/column scaling, Gaussian with
     power-of-two row/column scaling, and KKR-shaped blocks."""
-    from workloads import batched_problems, complex_normal, kkr_operands
+    from workloads import batched_problems, complex_normal
     rng = np.random.default_rng(seed)
     ms, ns, ks = pair_sizes(rng, count, mn_choices)
     fam = rng.integers(0, 4, count)
@@ -63,18 +85,74 @@ def generate_pairs(count: int, seed: int, mn_choices=(32, 64)):
             A = complex_normal(r, (m, k)) * np.ldexp(1.0, r.integers(-30, 31, m))[:, None]
             B = complex_normal(r, (k, n)) * np.ldexp(1.0, r.integers(-30, 31, n))[None, :]
         else:
-            nb = max(1, k // 32)
-            A_full, B_full = kkr_operands(nb, seed=sub, n_rhs=n)
-            A = np.ascontiguousarray(A_full[:m, :])
-            B = B_full
-            k = A.shape[1]
+            A, B = kkr_rows(m, n, k, sub)
         pairs.append((np.ascontiguousarray(A, dtype=np.complex128),
                       np.ascontiguousarray(B, dtype=np.complex128)))
     return pairs
 
 
+def generate_pairs_device(count: int, seed: int, mn_choices=(32, 64)):
+    """The same four families as generate_pairs, drawn on the GPU with a seeded
+    torch generator (training data only; the oracle-checked workloads use the
+    numpy generators). Returns a list of (A, B) complex128 CUDA tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    ms, ns, ks = pair_sizes(rng, count, mn_choices)
+    fam = rng.integers(0, 4, count)
+    two = torch.tensor(2.0, dtype=torch.float64, device="cuda")
+
+    def cn(shape):
+        re = torch.randn(shape, generator=gen, dtype=torch.float64, device="cuda")
+        im = torch.randn(shape, generator=gen, dtype=torch.float64, device="cuda")
+        return torch.complex(re, im) / math.sqrt(2.0)
+
+    def uni(shape, lo, hi):
+        return torch.rand(shape, generator=gen, dtype=torch.float64, device="cuda") * (hi - lo) + lo
+
+    def ints(shape, lo, hi):
+        return torch.randint(lo, hi + 1, shape, generator=gen, device="cuda").to(torch.float64)
+
+    out = []
+    for i in range(count):
+        m, n, k = int(ms[i]), int(ns[i]), int(ks[i])
+        f = fam[i]
+        if f == 0:
+            w = int(rng.integers(0, 13))
+            A = torch.complex(uni((m, k), -1, 1), uni((m, k), -1, 1)) * two.pow(ints((m, k), -w, w))
+            B = torch.complex(uni((k, n), -1, 1), uni((k, n), -1, 1)) * two.pow(ints((k, n), -w, w))
+        elif f == 1:
+            sa, sb = rng.uniform(0.0, 20.0, 2)
+            A = cn((m, k)) * two.pow(-torch.floor(sa * uni((m, k), 0, 1)))
+            A = A * two.pow(ints((m,), 0, int(sa)))[:, None]
+            B = cn((k, n)) * two.pow(-torch.floor(sb * uni((k, n), 0, 1)))
+            B = B * two.pow(ints((n,), 0, int(sb)))[None, :]
+        elif f == 2:
+            A = cn((m, k)) * two.pow(ints((m,), -30, 30))[:, None]
+            B = cn((k, n)) * two.pow(ints((n,), -30, 30))[None, :]
+        else:
+            rows = -(-m // 32) * 32
+            bi = torch.arange(rows, device="cuda") // 32
+            bj = torch.arange(k, device="cuda") // 32
+            G = cn((rows, k)) / (1.0 + (bi[:, None] - bj[None, :]).abs().to(torch.float64))
+            nbr = rows // 32
+            mag = torch.pow(10.0, uni((nbr, 32, 32), -3, 0))
+            ph = uni((nbr, 32, 32), 0, 2 * math.pi)
+            T = torch.polar(mag, ph)
+            TG = torch.bmm(T, G.reshape(nbr, 32, k).contiguous()).reshape(rows, k)
+            eye = torch.zeros((rows, k), dtype=torch.complex128, device="cuda")
+            d = min(rows, k)
+            eye[torch.arange(d), torch.arange(d)] = 1.0
+            A = (eye - TG)[:m]
+            B = cn((k, n))
+        out.append((A.contiguous(), B.contiguous()))
+    return out
+
+
 class DeviceBatch:
-    """Column-major device copies of a list of complex pairs in flat buffers."""
+    """Column-major device copies of a list of complex pairs in flat buffers
+    (pairs of numpy arrays or of CUDA tensors)."""
 
     def __init__(self, pairs):
         import torch
@@ -86,10 +164,12 @@ class DeviceBatch:
         self.oa = np.concatenate([[0], np.cumsum(sa)])
         self.ob = np.concatenate([[0], np.cumsum(sb)])
         self.oc = np.concatenate([[0], np.cumsum(sc)])
-        ha = np.concatenate([A.T.ravel() for A, _ in pairs])
-        hb = np.concatenate([B.T.ravel() for _, B in pairs])
-        self.A = torch.from_numpy(ha).cuda()
-        self.B = torch.from_numpy(hb).cuda()
+        if isinstance(pairs[0][0], np.ndarray):
+            self.A = torch.from_numpy(np.concatenate([A.T.ravel() for A, _ in pairs])).cuda()
+            self.B = torch.from_numpy(np.concatenate([B.T.ravel() for _, B in pairs])).cuda()
+        else:
+            self.A = torch.cat([A.t().contiguous().reshape(-1) for A, _ in pairs])
+            self.B = torch.cat([B.t().contiguous().reshape(-1) for _, B in pairs])
         self.Aabs = self.A.abs()
         self.Babs = self.B.abs()
         self.nc = int(self.oc[-1])
@@ -100,16 +180,26 @@ class DeviceBatch:
         return [base + int(o) * elem for o in off[:-1]]
 
 
-def label_pairs(pairs, target: float, s_lo: int = S_LO, s_hi: int = S_HI, chunk: int = 2048):
+def label_pairs(pairs, target: float, s_lo: int = S_LO, s_hi: int = S_HI, chunk: int = 2048,
+                with_features: bool = False):
     """Smallest s in [s_lo, s_hi] with componentwise error <= target for each
-    pair (s_hi + 1 when none reaches it), and the error table err[pair, s]."""
+    pair (s_hi + 1 when none reaches it), the error table err[pair, s] and,
+    if asked, the features of every pair (a CUDA tensor)."""
     import torch
     labels = np.zeros(len(pairs), dtype=np.int64)
     errs = np.zeros((len(pairs), s_hi - s_lo + 1))
+    feats = torch.zeros((len(pairs), 64), dtype=torch.float32, device="cuda") if with_features else None
     for c0 in range(0, len(pairs), chunk):
         sub = pairs[c0:c0 + chunk]
         db = DeviceBatch(sub)
         nb = len(sub)
+        if with_features:
+            pa0, pb0 = db.ptrs(db.A, db.oa, 16), db.ptrs(db.B, db.ob, 16)
+            for b in range(nb):
+                m, n, k = int(db.m[b]), int(db.n[b]), int(db.k[b])
+                rc = ozaki_features("z", "N", "N", m, n, k, pa0[b], m, pb0[b], k, feats[c0 + b])
+                if rc:
+                    raise OzakiError(rc, "ozaki_features")
         ref = torch.zeros(db.nc, dtype=torch.complex128, device="cuda")
         den = torch.zeros(db.nc, dtype=torch.float64, device="cuda")
         pa, pb = db.ptrs(db.A, db.oa, 16), db.ptrs(db.B, db.ob, 16)
@@ -138,6 +228,8 @@ def label_pairs(pairs, target: float, s_lo: int = S_LO, s_hi: int = S_HI, chunk:
         ok = errs[c0:c0 + nb] <= target
         first = np.where(ok.any(axis=1), ok.argmax(axis=1) + s_lo, s_hi + 1)
         labels[c0:c0 + nb] = first
+    if with_features:
+        return labels, errs, feats
     return labels, errs
 
 
@@ -224,6 +316,79 @@ def load(path):
     return z["theta"], float(z["margin"]), float(z["target"])
 
 
+def evaluate_gain(theta, margin, target, kappa=8.0, pairs=None, steps=5, log=None):
+    """Learned selector + probe versus the best fixed slice count on a batch.
+
+    The fixed policy uses the smallest uniform s with every problem within the
+    target (known from the true errors against the native FP64 product); the
+    learned policy is ozaki_zgemm_batched in automatic mode. Returns a dict
+    with slice counts, INT8 work, times and whether every problem meets the
+    target at the slice count it got."""
+    import torch
+    from . import ozaki_load_selector, ozaki_status_string
+    from workloads import batched_problems
+    if pairs is None:
+        pairs, _ = batched_problems(512, 1003)
+    labels, errs = label_pairs(pairs, target)
+    nb = len(pairs)
+    m = np.array([A.shape[0] for A, _ in pairs])
+    n = np.array([B.shape[1] for _, B in pairs])
+    k = np.array([A.shape[1] for A, _ in pairs])
+    work = 8.0 * m * n * k
+    s_fixed = int(min(labels.max(), S_HI))
+    db = DeviceBatch(pairs)
+    pa, pb = db.ptrs(db.A, db.oa, 16), db.ptrs(db.B, db.ob, 16)
+    out = torch.zeros(db.nc, dtype=torch.complex128, device="cuda")
+    po = db.ptrs(out, db.oc, 16)
+    rc = ozaki_load_selector(theta, margin, target, kappa)
+    if rc:
+        raise OzakiError(rc, "ozaki_load_selector")
+    used = []
+
+    def run_auto():
+        r = ozaki_zgemm_batched(["N"] * nb, ["N"] * nb, m, n, k, [1.0] * nb, pa, m, pb, k,
+                                [0.0] * nb, po, m, nb, None, used)
+        if r:
+            raise RuntimeError(ozaki_status_string(r))
+
+    def run_fixed():
+        r = ozaki_zgemm_batched(["N"] * nb, ["N"] * nb, m, n, k, [1.0] * nb, pa, m, pb, k,
+                                [0.0] * nb, po, m, nb, [s_fixed] * nb)
+        if r:
+            raise RuntimeError(ozaki_status_string(r))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    t_auto = timed(run_auto)
+    s_auto = np.array(used)
+    t_fixed = timed(run_fixed)
+    err_auto = np.array([errs[b, min(s_auto[b], S_HI) - S_LO] if s_auto[b] >= S_LO else np.inf
+                         for b in range(nb)])
+    pairs_of = lambda s: s * (s + 1) / 2
+    res = {
+        "problems": nb, "target": target, "s_fixed": s_fixed,
+        "mean_s_learned": float(s_auto.mean()), "mean_label": float(np.minimum(labels, S_HI).mean()),
+        "int8_ops_learned": float(np.sum(pairs_of(s_auto) * work)),
+        "int8_ops_fixed": float(np.sum(pairs_of(s_fixed) * work)),
+        "ms_learned": t_auto, "ms_fixed": t_fixed,
+        "all_within_target_learned": bool(np.all(err_auto <= target)),
+        "max_err_learned": float(err_auto.max()),
+        "problems_raised_by_probe_or_over_label": int(np.sum(s_auto > np.minimum(labels, S_HI))),
+        "problems_below_label": int(np.sum(s_auto < np.minimum(labels, S_HI))),
+    }
+    res["int8_work_ratio_learned_over_fixed"] = res["int8_ops_learned"] / res["int8_ops_fixed"]
+    if log:
+        log(res)
+    return res
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="train the slice-count selector on the GPU")
@@ -239,12 +404,24 @@ def main(argv=None):
         print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
 
     ntrain = int(args.pairs * 0.9)
-    log(f"generating {args.pairs} pairs")
-    pairs = generate_pairs(args.pairs, args.seed)
-    log("labelling")
-    labels, _ = label_pairs(pairs, args.target)
-    log(f"label histogram {np.bincount(labels, minlength=S_HI + 2)[S_LO:]}")
-    feats = features_of(pairs)
+    from . import ozaki_batched_graphs
+    import torch
+    ozaki_batched_graphs(False)          # one-off batches: no graph capture
+    chunk = 4096
+    feats_l, labels_l = [], []
+    for c0 in range(0, args.pairs, chunk):
+        cnt = min(chunk, args.pairs - c0)
+        pairs = generate_pairs_device(cnt, args.seed * 1000003 + c0)
+        lab, _, f = label_pairs(pairs, args.target, with_features=True)
+        feats_l.append(f)
+        labels_l.append(lab)
+        del pairs
+        if (c0 // chunk) % 8 == 0:
+            log(f"{c0 + cnt} pairs labelled")
+    feats = torch.cat(feats_l)
+    labels = np.concatenate(labels_l)
+    ozaki_batched_graphs(True)
+    log(f"label histogram (s = {S_LO}..{S_HI + 1}) {np.bincount(labels, minlength=S_HI + 2)[S_LO:]}")
     log("training")
     theta = train(feats[:ntrain], labels[:ntrain], epochs=args.epochs, seed=args.seed, log=log)
     pred = predict(theta, feats[ntrain:])
