@@ -69,7 +69,8 @@ enum ozaki_status {
   OZAKI_ERR_WORKSPACE = 3,    /* the caller's workspace is too small */
   OZAKI_ERR_NO_DEVICE = 4,    /* no usable gfx950 device */
   OZAKI_ERR_INTERNAL = 5,
-  OZAKI_ERR_NO_SELECTOR = 6   /* automatic slice selection without a loaded selector */
+  OZAKI_ERR_NO_SELECTOR = 6,  /* automatic slice selection without a loaded selector */
+  OZAKI_ERR_IO = 7            /* tuning cache file missing, unwritable or malformed */
 };
 
 /*
@@ -152,6 +153,46 @@ int ozaki_load_selector(const float *params, float margin, double target, double
 int ozaki_batched_graphs(int on);
 /* Release every cached batched plan and graph (device memory included). */
 int ozaki_batched_cache_clear(void);
+
+/*
+ * Tile autotuner of the fused slice GEMM. The paper takes its emulation
+ * library as shipped (Section 3.1); the tile candidates and the tuning table
+ * are this library's own.
+ * A tuning id is 2 * tile configuration + tile order; ozaki_tune_configs()
+ * gives their number. Every id computes bit-identical results: only the
+ * workgroup shape, the LDS ring depth and the order in which the persistent
+ * workgroups walk the output tiles differ.
+ * The table maps (kind, slices, bucket of m, of n' = n or 2n, of the 32-deep
+ * contraction blocks of k' = k or 2k; bucket = ceil(log2)) to an id; ozaki_dgemm,
+ * ozaki_zgemm and ozaki_debug_diagonals look their shape up there (default 0).
+ * The environment variable OZAKI_GEMM_CONFIG=<id> forces one id for every call;
+ * OZAKI_TUNE_CACHE=<file> loads a saved table before the first lookup.
+ * The batched path always uses id 0.
+ *
+ * ozaki_autotune: times every id on an m x n x k product with `slices` slices
+ *   on the library's stream (zeroed operands in the library workspace, a
+ *   temporary m x n output allocated and freed inside; the stream is
+ *   synchronised), keeps the fastest in the table and returns it in *best and
+ *   its time per launch in *best_ms (either may be NULL).
+ *   Errors: kind -1 ('d' or 'z'), m -2, n -3, k -4 (each >= 1), slices -5,
+ *   reps -6 (1..1000); OZAKI_ERR_* for device failures.
+ * ozaki_tune_set: records `id` for the bucket of the shape (id < 0 removes the
+ *   entry); id -6 if >= ozaki_tune_configs(). ozaki_tune_get: the id a call of
+ *   that shape would use (>= 0) or a negative argument error as for autotune.
+ * ozaki_tune_save / ozaki_tune_load: the table as a JSON file (path -1 if NULL;
+ *   OZAKI_ERR_IO if the file cannot be opened or is malformed). Loading merges
+ *   the entries into the table when the file's "arch" equals the current
+ *   device's architecture name and ignores them otherwise.
+ * The table is process-wide and not thread-safe.
+ */
+int ozaki_autotune(char kind, int64_t m, int64_t n, int64_t k, int slices, int reps, int *best,
+                   double *best_ms);
+int ozaki_tune_set(char kind, int64_t m, int64_t n, int64_t k, int slices, int id);
+int ozaki_tune_get(char kind, int64_t m, int64_t n, int64_t k, int slices);
+int ozaki_tune_configs(void);
+int ozaki_tune_save(const char *path);
+int ozaki_tune_load(const char *path);
+int ozaki_tune_clear(void);
 
 /*
  * Randomized FP64 residual probe of a computed product C ~ op(A) op(B)

@@ -27,7 +27,8 @@ __all__ = [
     "ozaki_batched_graphs", "ozaki_batched_cache_clear", "ozaki_probe", "ozaki_features",
     "ozaki_mlp_state_bytes", "ozaki_mlp_scratch_bytes", "ozaki_mlp_init", "ozaki_mlp_refresh",
     "ozaki_mlp_forward", "ozaki_mlp_backward", "ozaki_mlp_adam", "MLP_PARAMS",
-    "ozaki_load_selector",
+    "ozaki_load_selector", "ozaki_autotune", "ozaki_tune_set", "ozaki_tune_get",
+    "ozaki_tune_configs", "ozaki_tune_save", "ozaki_tune_load", "ozaki_tune_clear",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,6 +77,13 @@ _SIG = {
     "ozaki_mlp_backward": (_c.c_int, [_vp, _i64, _vp, _vp, _c.c_float, _vp, _vp]),
     "ozaki_mlp_adam": (_c.c_int, [_vp, _c.c_float, _c.c_float, _c.c_float, _c.c_float, _i64]),
     "ozaki_load_selector": (_c.c_int, [_vp, _c.c_float, _c.c_double, _c.c_double]),
+    "ozaki_autotune": (_c.c_int, [_c.c_char, _i64, _i64, _i64, _c.c_int, _c.c_int, _vp, _vp]),
+    "ozaki_tune_set": (_c.c_int, [_c.c_char, _i64, _i64, _i64, _c.c_int, _c.c_int]),
+    "ozaki_tune_get": (_c.c_int, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
+    "ozaki_tune_configs": (_c.c_int, []),
+    "ozaki_tune_save": (_c.c_int, [_c.c_char_p]),
+    "ozaki_tune_load": (_c.c_int, [_c.c_char_p]),
+    "ozaki_tune_clear": (_c.c_int, []),
     "ozaki_set_stream": (_c.c_int, [_vp]),
     "ozaki_set_workspace": (_c.c_int, [_vp, _c.c_size_t]),
     "ozaki_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
@@ -258,6 +266,41 @@ def ozaki_load_selector(params, margin, target, kappa) -> int:
         return -1
     return library().ozaki_load_selector(p.ctypes.data_as(_c.c_void_p), float(margin), float(target),
                                          float(kappa))
+
+
+def ozaki_autotune(kind, m, n, k, slices, reps=10):
+    """(status, best tuning id, ms per launch of the best id)."""
+    _bind_stream()
+    best = _c.c_int(-1)
+    ms = _c.c_double(0.0)
+    rc = library().ozaki_autotune(_ch(kind), m, n, k, int(slices), int(reps),
+                                  _c.cast(_c.pointer(best), _c.c_void_p),
+                                  _c.cast(_c.pointer(ms), _c.c_void_p))
+    return rc, best.value, ms.value
+
+
+def ozaki_tune_set(kind, m, n, k, slices, tune_id) -> int:
+    return library().ozaki_tune_set(_ch(kind), m, n, k, int(slices), int(tune_id))
+
+
+def ozaki_tune_get(kind, m, n, k, slices) -> int:
+    return library().ozaki_tune_get(_ch(kind), m, n, k, int(slices))
+
+
+def ozaki_tune_configs() -> int:
+    return library().ozaki_tune_configs()
+
+
+def ozaki_tune_save(path) -> int:
+    return library().ozaki_tune_save(None if path is None else os.fsencode(path))
+
+
+def ozaki_tune_load(path) -> int:
+    return library().ozaki_tune_load(None if path is None else os.fsencode(path))
+
+
+def ozaki_tune_clear() -> int:
+    return library().ozaki_tune_clear()
 
 
 def ozaki_set_stream(stream) -> int:

@@ -8,8 +8,10 @@
 // The interface mirrors a BLAS GEMM because the paper's solver reaches the
 // emulation through intercepted standard BLAS calls (Section 3.1).
 #include <algorithm>
+#include <array>
 #include <cctype>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <list>
@@ -28,6 +30,7 @@ constexpr int kMaxDev = 16;
 struct DevInfo {
   bool valid = false;
   int num_cu = 0;
+  char arch[64] = {};  // gcnArchName up to the first ':'
 };
 
 struct State {
@@ -95,6 +98,12 @@ int current_device(int *dev) {
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, *dev) != hipSuccess || cu <= 0)
       return OZAKI_ERR_NO_DEVICE;
     d.num_cu = cu;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return OZAKI_ERR_NO_DEVICE;
+    size_t i = 0;
+    for (; i + 1 < sizeof(d.arch) && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+      d.arch[i] = prop.gcnArchName[i];
+    d.arch[i] = 0;
     d.valid = true;
   }
   return OZAKI_OK;
@@ -210,20 +219,48 @@ View view_opB(const void *B, char trans, int64_t k, int64_t n, int64_t ldb, bool
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? OZAKI_OK : OZAKI_ERR_HIP; }
 
-// Tile configuration of the fused GEMM: OZAKI_GEMM_CONFIG overrides the
-// default (0) for experiments and tuning.
-int gemm_config(int S, int64_t m, int64_t nprime, int64_t nkb) {
-  (void)S;
-  (void)m;
-  (void)nprime;
-  (void)nkb;
+// ---------------------------------------------------------------- autotune
+// Tuning table of the fused GEMM: for each (real/complex, s, size bucket) the
+// fastest tuning id found by ozaki_autotune. A bucket is the ceiling of log2
+// of m, of the rows n' of B' and of the 32-deep contraction blocks.
+struct TuneEntry {
+  int id;
+  double ms;
+};
+using TuneKey = std::array<int, 5>;
+std::map<TuneKey, TuneEntry> g_tune;
+bool g_tune_env_loaded = false;
+
+int log2_bucket(int64_t x) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+TuneKey tune_key(bool cplx, int S, int64_t m, int64_t nprime, int64_t nkb) {
+  return {cplx ? 1 : 0, S, log2_bucket(m), log2_bucket(nprime), log2_bucket(nkb)};
+}
+
+int tune_load(const char *path);
+
+// Tuning id of one emulated product: OZAKI_GEMM_CONFIG (a tuning id) wins,
+// then the tuning table (seeded once from the file named by OZAKI_TUNE_CACHE),
+// then the default 0.
+int gemm_config(bool cplx, int S, int64_t m, int64_t nprime, int64_t nkb) {
   static int env = -2;
   if (env == -2) {
     const char *e = getenv("OZAKI_GEMM_CONFIG");
     env = (e != nullptr && *e) ? atoi(e) : -1;
     if (env >= gemm_num_configs()) env = -1;
   }
-  return env >= 0 ? env : 0;
+  if (env >= 0) return env;
+  if (!g_tune_env_loaded) {
+    g_tune_env_loaded = true;
+    const char *f = getenv("OZAKI_TUNE_CACHE");
+    if (f != nullptr && *f) (void)tune_load(f);
+  }
+  const auto it = g_tune.find(tune_key(cplx, S, m, nprime, nkb));
+  return it == g_tune.end() ? 0 : it->second.id;
 }
 
 // BLAS argument checks; returns 0 or -(argument number).
@@ -324,7 +361,7 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
   if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
   const GemmArgs ga = gemm_args(p, ws, ar, ai, br, bi, beta_zero, C, ldc, nullptr);
   const int mk = phase_begin(OZAKI_PHASE_GEMM, g.stream);
-  rc = hip_rc(launch_ozgemm(slices, gemm_config(slices, m, p.nprime, p.nkb), ga,
+  rc = hip_rc(launch_ozgemm(slices, gemm_config(cplx, slices, m, p.nprime, p.nkb), ga,
                             g.dev[dev].num_cu, g.stream));
   phase_end(mk, g.stream);
   if (g_tm.on) ++g_tm.calls;
@@ -983,6 +1020,143 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
   return OZAKI_OK;
 }
 
+// Tuning cache file (JSON). One entry per line so that the reader below can
+// take it line by line; any JSON reader can read it too:
+//   {"format": "ozaki-tune-1", "arch": "gfx950", "entries": [
+//    {"kind": "z", "slices": 7, "mb": 11, "nb": 12, "kb": 7, "id": 0, "ms": 0.8205},
+//    ...]}
+// Entries of another architecture are ignored.
+int tune_load(const char *path) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  FILE *f = fopen(path, "r");
+  if (f == nullptr) return OZAKI_ERR_IO;
+  char line[512];
+  bool arch_ok = false, seen_arch = false;
+  std::map<TuneKey, TuneEntry> got;
+  while (fgets(line, sizeof line, f) != nullptr) {
+    const char *a = strstr(line, "\"arch\"");
+    if (a != nullptr) {
+      char arch[64] = {};
+      if (sscanf(a, "\"arch\": \"%63[^\"]\"", arch) != 1) {
+        fclose(f);
+        return OZAKI_ERR_IO;
+      }
+      seen_arch = true;
+      arch_ok = strcmp(arch, g.dev[dev].arch) == 0;
+    }
+    const char *e = strstr(line, "{\"kind\"");
+    if (e == nullptr) continue;
+    char kind = 0;
+    int S, mb, nb, kb, id;
+    double ms;
+    if (sscanf(e, "{\"kind\": \"%c\", \"slices\": %d, \"mb\": %d, \"nb\": %d, \"kb\": %d, "
+                  "\"id\": %d, \"ms\": %lf}",
+               &kind, &S, &mb, &nb, &kb, &id, &ms) != 7 ||
+        (kind != 'd' && kind != 'z') || S < 1 || S > OZAKI_S_MAX || id < 0 ||
+        id >= gemm_num_configs()) {
+      fclose(f);
+      return OZAKI_ERR_IO;
+    }
+    got[{kind == 'z' ? 1 : 0, S, mb, nb, kb}] = TuneEntry{id, ms};
+  }
+  fclose(f);
+  if (!seen_arch) return OZAKI_ERR_IO;
+  if (arch_ok)
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+  return OZAKI_OK;
+}
+
+int tune_save(const char *path) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  FILE *f = fopen(path, "w");
+  if (f == nullptr) return OZAKI_ERR_IO;
+  fprintf(f, "{\"format\": \"ozaki-tune-1\", \"arch\": \"%s\", \"entries\": [\n", g.dev[dev].arch);
+  size_t i = 0;
+  for (const auto &kv : g_tune) {
+    const TuneKey &k = kv.first;
+    fprintf(f,
+            " {\"kind\": \"%c\", \"slices\": %d, \"mb\": %d, \"nb\": %d, \"kb\": %d, \"id\": %d, "
+            "\"ms\": %.6f}%s\n",
+            k[0] ? 'z' : 'd', k[1], k[2], k[3], k[4], kv.second.id, kv.second.ms,
+            ++i < g_tune.size() ? "," : "");
+  }
+  fprintf(f, "]}\n");
+  return fclose(f) == 0 ? OZAKI_OK : OZAKI_ERR_IO;
+}
+
+// Times every tuning id of the fused GEMM on one shape (operands zeroed: the
+// kernel's time does not depend on the values) and records the fastest.
+int autotune(bool cplx, int64_t m, int64_t n, int64_t k, int S, int reps, int *best,
+             double *best_ms) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  const Plan p = make_plan(cplx, m, n, k, S, g.dev[dev].num_cu);
+  void *wsv = nullptr;
+  if ((rc = get_workspace(p.total, &wsv))) return rc;
+  char *ws = static_cast<char *>(wsv);
+  const hipStream_t st = g.stream;
+  if ((rc = hip_rc(launch_fill_i32(reinterpret_cast<int *>(ws), (int64_t)(p.total / 4), 0, st))))
+    return rc;
+  void *C = nullptr;
+  const size_t cbytes = (size_t)m * n * (cplx ? 16 : 8);
+  if (hipMalloc(&C, cbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return OZAKI_ERR_ALLOC;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = OZAKI_ERR_HIP;
+  const GemmArgs ga = gemm_args(p, ws, 1.0, 0.0, 0.0, 0.0, true, C, m, nullptr);
+  int best_id = -1;
+  double best_t = 0.0;
+  for (int id = 0; rc == OZAKI_OK && id < gemm_num_configs(); ++id) {
+    double t_id = 0.0;
+    for (int trial = 0; rc == OZAKI_OK && trial < 3; ++trial) {
+      // trial 0 is a warm-up launch pair, trials 1 and 2 are timed
+      const int nl = trial == 0 ? 2 : reps;
+      if ((rc = hip_rc(hipEventRecord(e0, st)))) break;
+      for (int r = 0; rc == OZAKI_OK && r < nl; ++r)
+        rc = hip_rc(launch_ozgemm(S, id, ga, g.dev[dev].num_cu, st));
+      if (rc) break;
+      if ((rc = hip_rc(hipEventRecord(e1, st)))) break;
+      if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
+      float msf = 0.f;
+      if ((rc = hip_rc(hipEventElapsedTime(&msf, e0, e1)))) break;
+      if (trial > 0) {
+        const double t = (double)msf / nl;
+        t_id = trial == 1 ? t : std::min(t_id, t);
+      }
+    }
+    if (rc == OZAKI_OK && (best_id < 0 || t_id < best_t)) {
+      best_id = id;
+      best_t = t_id;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (hipFree(C) != hipSuccess && rc == OZAKI_OK) rc = OZAKI_ERR_HIP;
+  if (rc) return rc;
+  g_tune[tune_key(cplx, S, m, p.nprime, p.nkb)] = TuneEntry{best_id, best_t};
+  if (best) *best = best_id;
+  if (best_ms) *best_ms = best_t;
+  return OZAKI_OK;
+}
+
+int tune_shape(char kind, int64_t m, int64_t n, int64_t k, int slices, bool *cplx) {
+  kind = up(kind);
+  if (kind != 'D' && kind != 'Z') return -1;
+  if (m <= 0) return -2;
+  if (n <= 0) return -3;
+  if (k <= 0) return -4;
+  if (slices < 1 || slices > OZAKI_S_MAX) return -5;
+  *cplx = kind == 'Z';
+  return OZAKI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1053,6 +1227,54 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
   if (rc == OZAKI_OK && slices_used != nullptr)
     for (int64_t b = 0; b < batch; ++b) slices_used[b] = slices[b];
   return rc;
+}
+
+int ozaki_autotune(char kind, int64_t m, int64_t n, int64_t k, int slices, int reps, int *best,
+                   double *best_ms) {
+  bool cplx = false;
+  int rc = tune_shape(kind, m, n, k, slices, &cplx);
+  if (rc) return rc;
+  if (reps < 1 || reps > 1000) return -6;
+  return autotune(cplx, m, n, k, slices, reps, best, best_ms);
+}
+
+int ozaki_tune_set(char kind, int64_t m, int64_t n, int64_t k, int slices, int id) {
+  bool cplx = false;
+  int rc = tune_shape(kind, m, n, k, slices, &cplx);
+  if (rc) return rc;
+  if (id >= gemm_num_configs()) return -6;
+  const Plan p = make_plan(cplx, m, n, k, slices, 1);
+  const TuneKey key = tune_key(cplx, slices, m, p.nprime, p.nkb);
+  if (id < 0)
+    g_tune.erase(key);
+  else
+    g_tune[key] = TuneEntry{id, 0.0};
+  return OZAKI_OK;
+}
+
+int ozaki_tune_get(char kind, int64_t m, int64_t n, int64_t k, int slices) {
+  bool cplx = false;
+  int rc = tune_shape(kind, m, n, k, slices, &cplx);
+  if (rc) return rc;
+  const Plan p = make_plan(cplx, m, n, k, slices, 1);
+  return gemm_config(cplx, slices, m, p.nprime, p.nkb);
+}
+
+int ozaki_tune_configs(void) { return gemm_num_configs(); }
+
+int ozaki_tune_save(const char *path) {
+  if (path == nullptr) return -1;
+  return tune_save(path);
+}
+
+int ozaki_tune_load(const char *path) {
+  if (path == nullptr) return -1;
+  return tune_load(path);
+}
+
+int ozaki_tune_clear(void) {
+  g_tune.clear();
+  return OZAKI_OK;
 }
 
 int ozaki_load_selector(const float *params, float margin, double target, double kappa) {
@@ -1278,6 +1500,7 @@ const char *ozaki_status_string(int status) {
     case OZAKI_ERR_NO_DEVICE: return "no usable device";
     case OZAKI_ERR_INTERNAL: return "internal error";
     case OZAKI_ERR_NO_SELECTOR: return "automatic slice selection needs a loaded selector";
+    case OZAKI_ERR_IO: return "tuning cache file missing, unwritable or malformed";
     default: return "unknown status";
   }
 }
@@ -1348,7 +1571,8 @@ int ozaki_debug_diagonals(char kind, char transa, char transb, int64_t m, int64_
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
   if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
   const GemmArgs ga = gemm_args(p, ws, 1.0, 0.0, 0.0, 0.0, true, nullptr, m, S);
-  return hip_rc(launch_ozgemm(slices, gemm_config(slices, m, p.nprime, p.nkb), ga,
+  // raw diagonal output exists in tile configuration 0 only (either order)
+  return hip_rc(launch_ozgemm(slices, gemm_config(cplx, slices, m, p.nprime, p.nkb) & 1, ga,
                               g.dev[dev].num_cu, g.stream));
 }
 

@@ -30,7 +30,7 @@
 // memory. The FP64 epilogue converts every S_t exactly (|S_t| < 2^53) and adds
 // them largest weight first, one rounding per addition, then scales by
 // 2^(e_i + f_j) and applies alpha/beta without fused multiply-adds.
-#include "ozaki_internal.hpp"
+#include "ozaki_gemm_tile.hpp"
 
 namespace oz {
 
@@ -54,19 +54,9 @@ struct Cfg {
   static_assert(MINW < 64, "vmcnt immediate (6 bits)");
 };
 
-// Wait until at most N vector-memory operations of this wave are in flight.
-// Inline assembly with a memory clobber: the compiler neither moves memory
-// accesses across it nor adds a drain of the LDS copies still in flight.
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
-
-// Contraction blocks of 32 a chunk may hold: S * 32 * kb * 127^2 <= 2^31 - 1.
-__host__ __device__ constexpr int64_t chunk_blocks(int S) {
-  return (int64_t)(2147483647ll / ((int64_t)S * 32 * 127 * 127));
-}
+using tile::barrier_only;
+using tile::chunk_blocks;
+using tile::wait_vmcnt;
 
 template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED>
 __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
@@ -74,7 +64,7 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
   __shared__ __attribute__((aligned(16))) int8_t lds[C_::LDS];
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
   const int wj = wave % WJ;
   const int wi = wave / WJ;
 
@@ -83,14 +73,13 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
       GROUPED ? G.ntiles
               : ((G.one.nprime + C_::BJ - 1) / C_::BJ) * ((G.one.m + C_::BI - 1) / C_::BI);
 
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int64_t tn = blockIdx.x; tn < ntiles; tn += gridDim.x) {
     // The problem this tile belongs to (uniform across the workgroup, so the
     // descriptor is fetched with scalar loads).
-    const GemmProblem a = GROUPED ? G.probs[G.tile_prob[tile]] : G.one;
-    const int64_t local = GROUPED ? (int64_t)G.tile_local[tile] : tile;
-    const int64_t nti = (a.m + C_::BI - 1) / C_::BI;
-    const int64_t tj = local / nti;
-    const int64_t ti = local % nti;
+    const GemmProblem a = GROUPED ? G.probs[G.tile_prob[tn]] : G.one;
+    const int64_t local = GROUPED ? (int64_t)G.tile_local[tn] : tn;
+    int64_t tj, ti;
+    tile::tile_coords(local, G.order, a.m, a.nprime, C_::BJ, C_::BI, tj, ti);
     const int64_t nkb = a.nkb;
 
     // Copy of contraction block kb into LDS stage `buf`: fragment f lands at
@@ -123,24 +112,10 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
       for (int t = 0; t < S; ++t) acc[ib][t] = v16i{0};
 
     // Exact int64 carry of the INT32 accumulators (chunked contraction only).
-    // All carry traffic uses device-scope atomics, so it goes to L2 and never
-    // meets a stale line in the non-coherent vector L1.
     int64_t *ws = G.flush_ws + ((int64_t)blockIdx.x * C_::NW + wave) * (int64_t)IB * S * 1024;
     auto carry = [&](bool first) {
 #pragma unroll
-      for (int ib = 0; ib < IB; ++ib)
-#pragma unroll
-      for (int t = 0; t < S; ++t) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          int64_t *p = ws + ((ib * S + t) * 16 + r) * 64 + lane;
-          if (first)
-            __hip_atomic_store(p, (int64_t)acc[ib][t][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          else
-            __hip_atomic_fetch_add(p, (int64_t)acc[ib][t][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        acc[ib][t] = v16i{0};
-      }
+      for (int ib = 0; ib < IB; ++ib) tile::carry_block<S>(acc[ib], ws + ib * S * 1024, lane, first);
     };
 
     constexpr int D = NBUF - 1;  // prefetch distance in contraction blocks
@@ -203,105 +178,15 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
     if constexpr (chunked) carry(!carried);
 
     // ------------------------------------------------------------ epilogue
-    auto epilogue = [&](int ib) {
-      const int64_t i = ti * C_::BI + (wi * IB + ib) * 32 + (lane & 31);
-      const int64_t jbase = tj * C_::BJ + wj * 32 + 4 * (lane >> 5);
-      const bool row_ok = i < a.m;
-      const int codeA = row_ok ? a.codeA[i] : 0;
-
-      auto total = [&](int t, int r) -> int64_t {
-        if constexpr (chunked)
-          return __hip_atomic_load(ws + ((ib * S + t) * 16 + r) * 64 + lane, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        return (int64_t)acc[ib][t][r];
-      };
-
-      if constexpr (RAW) {
-        // Debug output of the exact diagonals.
-        if (row_ok) {
-  #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int64_t jp = jbase + 8 * (r >> 2) + (r & 3);
-            if (jp >= a.nprime) continue;
-  #pragma unroll
-            for (int t = 0; t < S; ++t) {
-              const int64_t v = total(t, r);
-              if (a.cplx) {
-                const int64_t n = a.nprime >> 1;
-                a.raw[(((int64_t)t * n + (jp >> 1)) * a.m + i) * 2 + (jp & 1)] = v;
-              } else {
-                a.raw[((int64_t)t * a.nprime + jp) * a.m + i] = v;
-              }
-            }
-          }
-        }
-        return;
-      }
-
-      double val[16];
-  #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double acc64 = 0.0;
-  #pragma unroll
-        for (int t = 0; t < S; ++t)
-          acc64 = add_rn(acc64, ldexp((double)total(t, r), -kDigitBits * (t + 2)));
-        val[r] = acc64;
-      }
-      if (!row_ok) return;
-      const int ea = code_exp(codeA);
-      const bool bad_i = code_bad(codeA);
-
-      if (a.cplx) {
-        double2 *C = reinterpret_cast<double2 *>(a.C);
-        const int64_t n = a.nprime >> 1;
-  #pragma unroll
-        for (int r = 0; r < 16; r += 2) {
-          const int64_t jp = jbase + 8 * (r >> 2) + (r & 3);
-          const int64_t j = jp >> 1;
-          if (j >= n) continue;
-          const int cb = a.codeB[j];
-          double2 *cp = C + i + j * a.ldc;
-          if (bad_i || code_bad(cb)) {
-            *cp = make_double2(qnan(), qnan());
-            continue;
-          }
-          const int sc = ea + code_exp(cb);
-          const double pr = ldexp(val[r], sc);
-          const double pi = ldexp(val[r + 1], sc);
-          double re = sub_rn(mul_rn(a.ar, pr), mul_rn(a.ai, pi));
-          double im = add_rn(mul_rn(a.ar, pi), mul_rn(a.ai, pr));
-          if (!a.beta_zero) {
-            const double2 z = *cp;
-            re = add_rn(re, sub_rn(mul_rn(a.br, z.x), mul_rn(a.bi, z.y)));
-            im = add_rn(im, add_rn(mul_rn(a.br, z.y), mul_rn(a.bi, z.x)));
-          }
-          *cp = make_double2(re, im);
-        }
-      } else {
-        double *C = reinterpret_cast<double *>(a.C);
-  #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t j = jbase + 8 * (r >> 2) + (r & 3);
-          if (j >= a.nprime) continue;
-          const int cb = a.codeB[j];
-          double *cp = C + i + j * a.ldc;
-          if (bad_i || code_bad(cb)) {
-            *cp = qnan();
-            continue;
-          }
-          const double p = ldexp(val[r], ea + code_exp(cb));
-          double out = mul_rn(a.ar, p);
-          if (!a.beta_zero) out = add_rn(out, mul_rn(a.br, *cp));
-          *cp = out;
-        }
-      }
-    };
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib) epilogue(ib);
+    for (int ib = 0; ib < IB; ++ib)
+      tile::store_block<S, CHUNKED, RAW>(a, acc[ib], ws + ib * S * 1024, lane,
+                                         ti * C_::BI + (wi * IB + ib) * 32 + (lane & 31),
+                                         tj * C_::BJ + wj * 32 + 4 * (lane >> 5));
   }
 }
 
-template <int S, int WJ, int WI, int IB, int NBUF>
+template <int S, int WJ, int WI, int IB, int NBUF, bool WITH_RAW>
 hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
   const bool grouped = a.probs != nullptr;
@@ -318,10 +203,14 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
     else
       hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, true>), g, b, 0, st, a);
   } else if (a.one.raw != nullptr) {
-    if (a.chunked)
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true, false>), g, b, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false, false>), g, b, 0, st, a);
+    if constexpr (WITH_RAW) {
+      if (a.chunked)
+        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true, false>), g, b, 0, st, a);
+      else
+        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false, false>), g, b, 0, st, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
     if (a.chunked)
       hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, false>), g, b, 0, st, a);
@@ -331,88 +220,88 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Tile configurations. All use 32 x 32 x 32 INT8 MFMA blocks and one INT32
-// accumulator set per diagonal.
-//   0: 8 waves (4 along j', 2 along i), one 32 x 32 block each, two waves per
-//      SIMD; workgroup tile 128 j' x 64 i.
-//   1: 4 waves along j', two 32 x 32 blocks along i each (the B' fragments of
-//      a wave feed both), one wave per SIMD; workgroup tile 128 j' x 64 i.
-//   2: 2 x 2 waves with two blocks along i each; workgroup tile 64 j' x 128 i.
-// The LDS ring holds three contraction blocks when it fits in 160 KiB, two
-// otherwise.
-constexpr int kNumCfg = 1;
+// Tile configurations (the autotuner's candidates). All use 32 x 32 x 32 INT8
+// MFMA blocks, one INT32 accumulator set per diagonal and 8 waves (two per
+// SIMD), one 32 x 32 output block per wave:
+//   0: 4 waves along j' x 2 along i (workgroup tile 128 j' x 64 i), LDS ring of
+//      three contraction blocks where it fits in 160 KiB (S <= 8), else two
+//   1: 2 along j' x 4 along i (64 j' x 128 i), same ring
+//   2: as 0 with a ring of two blocks (prefetch distance one)
+//   3: the one-wave-per-SIMD kernel of ozaki_gemm_w1.hip (same 128 j' x 64 i
+//      tile, two blocks per wave, fragments double-buffered in registers) for
+//      S <= 8 without contraction chunking; configuration 0 otherwise
+// A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
+// down the rows i, 1: along the columns j').
+constexpr int kNumCfg = 4;
 
-template <int S, int CFG>
+template <int CFG>
 struct Pick;
-template <int S>
-struct Pick<S, 0> {
-  static constexpr int WJ = 4, WI = 2, IB = 1;
+template <>
+struct Pick<0> {
+  static constexpr int WJ = 4, WI = 2, IB = 1, RING = 3;
 };
-template <int S>
-struct Pick<S, 1> {
-  static constexpr int WJ = 4, WI = 1, IB = 2;
+template <>
+struct Pick<1> {
+  static constexpr int WJ = 2, WI = 4, IB = 1, RING = 3;
 };
-template <int S>
-struct Pick<S, 2> {
-  static constexpr int WJ = 2, WI = 2, IB = 2;
+template <>
+struct Pick<2> {
+  static constexpr int WJ = 4, WI = 2, IB = 1, RING = 2;
 };
 
 template <int S, int CFG>
 constexpr int nbuf_for() {
-  using P = Pick<S, CFG>;
-  return S * (P::WJ + P::WI * P::IB) * kFragBytes * 3 <= 160 * 1024 ? 3 : 2;
+  using P = Pick<CFG>;
+  return (P::RING == 3 && S * (P::WJ + P::WI * P::IB) * kFragBytes * 3 <= 160 * 1024) ? 3 : 2;
 }
 
 template <int S, int CFG>
 hipError_t launch_pick(const GemmArgs &a, int num_cu, hipStream_t st) {
-  using P = Pick<S, CFG>;
-  return launch_cfg<S, P::WJ, P::WI, P::IB, nbuf_for<S, CFG>()>(a, num_cu, st);
+  using P = Pick<CFG>;
+  return launch_cfg<S, P::WJ, P::WI, P::IB, nbuf_for<S, CFG>(), CFG == 0>(a, num_cu, st);
 }
 
 template <int S>
 hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
-  (void)cfg;
-  return launch_pick<S, 0>(a, num_cu, st);
+  switch (cfg) {
+    case 1: return launch_pick<S, 1>(a, num_cu, st);
+    case 2: return launch_pick<S, 2>(a, num_cu, st);
+    case 3:
+      if (S <= gemm_w1_max_slices() && a.probs == nullptr && a.one.raw == nullptr && !a.chunked)
+        return launch_ozgemm_w1(S, a, num_cu, st);
+      return launch_pick<S, 0>(a, num_cu, st);
+    default: return launch_pick<S, 0>(a, num_cu, st);
+  }
 }
 
-template <int S>
-size_t flush_bytes_s(int cfg, int num_cu) {
-  (void)cfg;
-  const int per = Pick<S, 0>::WJ * Pick<S, 0>::WI * Pick<S, 0>::IB;
-  return (size_t)num_cu * per * (size_t)S * 1024 * sizeof(int64_t);
+template <int CFG>
+constexpr int waves_of() {
+  return Pick<CFG>::WJ * Pick<CFG>::WI * Pick<CFG>::IB;
 }
 
 }  // namespace
 
 int64_t kb_chunk_for(int S) { return chunk_blocks(S); }
 
-int gemm_num_configs() { return kNumCfg; }
+int gemm_num_configs() { return 2 * kNumCfg; }
 
 size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
   // the largest per-workgroup carry space over the configurations, so that a
   // plan is valid whichever configuration runs
   (void)cfg;
-  size_t mx = 0;
-  for (int c = 0; c < kNumCfg; ++c) {
-    size_t b = 0;
-    switch (S) {
-#define OZ_CASE(N) \
-  case N: b = flush_bytes_s<N>(c, num_cu); break;
-      OZ_CASE(1) OZ_CASE(2) OZ_CASE(3) OZ_CASE(4) OZ_CASE(5) OZ_CASE(6)
-      OZ_CASE(7) OZ_CASE(8) OZ_CASE(9) OZ_CASE(10) OZ_CASE(11) OZ_CASE(12)
-#undef OZ_CASE
-      default: break;
-    }
-    mx = std::max(mx, b);
-  }
-  return mx;
+  const int waves = std::max(waves_of<0>(), std::max(waves_of<1>(), waves_of<2>()));
+  return (size_t)num_cu * waves * (size_t)S * 1024 * sizeof(int64_t);
 }
 
 int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
   (void)S;
-  (void)cfg;
-  using P = Pick<1, 0>;
-  const int64_t BJ = 32 * P::WJ, BI = 32 * P::WI * P::IB;
+  int64_t BJ, BI;
+  switch (cfg / 2) {
+    case 1: BJ = 32 * Pick<1>::WJ; BI = 32 * Pick<1>::WI * Pick<1>::IB; break;
+    case 2: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
+    case 3: BJ = gemm_w1_tile_j(); BI = gemm_w1_tile_i(); break;
+    default: BJ = 32 * Pick<0>::WJ; BI = 32 * Pick<0>::WI * Pick<0>::IB; break;
+  }
   return ((nprime + BJ - 1) / BJ) * ((m + BI - 1) / BI);
 }
 
@@ -420,7 +309,10 @@ hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, 
   return launch_ozgemm(S, cfg, a, num_cu, st);
 }
 
-hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
+hipError_t launch_ozgemm(int S, int tune_id, const GemmArgs &a0, int num_cu, hipStream_t st) {
+  GemmArgs a = a0;
+  a.order = tune_id & 1;
+  const int cfg = tune_id >> 1;
   switch (S) {
 #define OZ_CASE(N) \
   case N: return launch_s<N>(cfg, a, num_cu, st);

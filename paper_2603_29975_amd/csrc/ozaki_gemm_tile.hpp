@@ -1,0 +1,168 @@
+// Pieces shared by the fused slice GEMM kernels of libozaki (gfx950): explicit
+// wait/barrier primitives, the INT32 chunk bound, the int64 carry of a 32 x 32
+// accumulator block and the FP64 recombination epilogue of one block.
+//
+// Accumulator layout of v_mfma_i32_32x32x32_i8 as used here: the MFMA row
+// index is the output column side j', the MFMA column index (lane % 32) is the
+// output row i. Register r of a lane holds j' = jbase + 8 (r / 4) + r % 4 with
+// jbase = 32 * block + 4 * (lane / 32).
+#pragma once
+
+#include "ozaki_internal.hpp"
+
+namespace oz {
+namespace tile {
+
+// Wait until at most N vector-memory operations of this wave are in flight.
+// Inline assembly with a memory clobber: the compiler neither moves memory
+// accesses across it nor adds a drain of the LDS copies still in flight.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+// Wait until this wave's LDS reads have returned.
+__device__ __forceinline__ void wait_lgkm0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
+
+// Contraction blocks of 32 a chunk may hold: S * 32 * kb * 127^2 <= 2^31 - 1.
+__host__ __device__ constexpr int64_t chunk_blocks(int S) {
+  return (int64_t)(2147483647ll / ((int64_t)S * 32 * 127 * 127));
+}
+
+// Exact int64 carry of one block's S INT32 accumulator sets into its carry
+// space `ws` (S * 16 * 64 int64, lane-interleaved); the accumulators restart
+// at zero. Device-scope atomics keep the traffic in L2, away from stale lines
+// of the non-coherent vector L1.
+template <int S>
+__device__ __forceinline__ void carry_block(v16i (&acc)[S], int64_t *ws, int lane, bool first) {
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int64_t *p = ws + (t * 16 + r) * 64 + lane;
+      if (first)
+        __hip_atomic_store(p, (int64_t)acc[t][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_fetch_add(p, (int64_t)acc[t][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    acc[t] = v16i{0};
+  }
+}
+
+// Recombination and store of one 32 x 32 block: row i of the output, lane
+// register r at column side j' = jbase + 8 (r / 4) + r % 4. Diagonal t + 2 of
+// the block is acc[t] (or, for a chunked contraction, the int64 total in the
+// carry space `ws`). acc = RN(acc + S_t 2^-7t) for t = 2..S+1, then
+// ldexp(acc, e_i + f_j) and alpha/beta without fused multiply-adds; rows or
+// columns flagged non-finite give NaN. RAW writes the exact diagonals instead.
+template <int S, bool CHUNKED, bool RAW>
+__device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&acc)[S],
+                                            const int64_t *ws, int lane, int64_t i,
+                                            int64_t jbase) {
+  const bool row_ok = i < a.m;
+  const int codeA = row_ok ? a.codeA[i] : 0;
+
+  auto total = [&](int t, int r) -> int64_t {
+    if constexpr (CHUNKED)
+      return __hip_atomic_load(ws + (t * 16 + r) * 64 + lane, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    return (int64_t)acc[t][r];
+  };
+
+  if constexpr (RAW) {
+    if (row_ok) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t jp = jbase + 8 * (r >> 2) + (r & 3);
+        if (jp >= a.nprime) continue;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          const int64_t v = total(t, r);
+          if (a.cplx) {
+            const int64_t n = a.nprime >> 1;
+            a.raw[(((int64_t)t * n + (jp >> 1)) * a.m + i) * 2 + (jp & 1)] = v;
+          } else {
+            a.raw[((int64_t)t * a.nprime + jp) * a.m + i] = v;
+          }
+        }
+      }
+    }
+    return;
+  }
+
+  double val[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double acc64 = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      acc64 = add_rn(acc64, ldexp((double)total(t, r), -kDigitBits * (t + 2)));
+    val[r] = acc64;
+  }
+  if (!row_ok) return;
+  const int ea = code_exp(codeA);
+  const bool bad_i = code_bad(codeA);
+
+  if (a.cplx) {
+    double2 *C = reinterpret_cast<double2 *>(a.C);
+    const int64_t n = a.nprime >> 1;
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+      const int64_t jp = jbase + 8 * (r >> 2) + (r & 3);
+      const int64_t j = jp >> 1;
+      if (j >= n) continue;
+      const int cb = a.codeB[j];
+      double2 *cp = C + i + j * a.ldc;
+      if (bad_i || code_bad(cb)) {
+        *cp = make_double2(qnan(), qnan());
+        continue;
+      }
+      const int sc = ea + code_exp(cb);
+      const double pr = ldexp(val[r], sc);
+      const double pi = ldexp(val[r + 1], sc);
+      double re = sub_rn(mul_rn(a.ar, pr), mul_rn(a.ai, pi));
+      double im = add_rn(mul_rn(a.ar, pi), mul_rn(a.ai, pr));
+      if (!a.beta_zero) {
+        const double2 z = *cp;
+        re = add_rn(re, sub_rn(mul_rn(a.br, z.x), mul_rn(a.bi, z.y)));
+        im = add_rn(im, add_rn(mul_rn(a.br, z.y), mul_rn(a.bi, z.x)));
+      }
+      *cp = make_double2(re, im);
+    }
+  } else {
+    double *C = reinterpret_cast<double *>(a.C);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t j = jbase + 8 * (r >> 2) + (r & 3);
+      if (j >= a.nprime) continue;
+      const int cb = a.codeB[j];
+      double *cp = C + i + j * a.ldc;
+      if (bad_i || code_bad(cb)) {
+        *cp = qnan();
+        continue;
+      }
+      const double p = ldexp(val[r], ea + code_exp(cb));
+      double out = mul_rn(a.ar, p);
+      if (!a.beta_zero) out = add_rn(out, mul_rn(a.br, *cp));
+      *cp = out;
+    }
+  }
+}
+
+// Output tile (tj, ti) of tile number `local` in a grid of tiles BJ x BI:
+// order 0 walks down the rows i first, order 1 along the columns j' first.
+__device__ __forceinline__ void tile_coords(int64_t local, int order, int64_t m, int64_t nprime,
+                                            int BJ, int BI, int64_t &tj, int64_t &ti) {
+  if (order == 0) {
+    const int64_t nti = (m + BI - 1) / BI;
+    tj = local / nti;
+    ti = local % nti;
+  } else {
+    const int64_t ntj = (nprime + BJ - 1) / BJ;
+    ti = local / ntj;
+    tj = local % ntj;
+  }
+}
+
+}  // namespace tile
+}  // namespace oz

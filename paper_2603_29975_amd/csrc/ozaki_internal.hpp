@@ -81,6 +81,7 @@ struct GemmArgs {
   int64_t *flush_ws;  // int64 per-workgroup carry space (chunked K only)
   int64_t kb_chunk;   // contraction blocks per exact INT32 chunk
   int chunked;        // some problem has nkb > kb_chunk
+  int order;          // tile order (set from the tuning id at launch)
 };
 
 // Tile counts of a problem for a configuration (host side).
@@ -91,12 +92,20 @@ hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, 
 // Contraction blocks (of 32) that one INT32 accumulation may cover for S
 // slices: S * 32 * kb * 127^2 < 2^31.
 int64_t kb_chunk_for(int S);
-// Tile configurations of the fused GEMM (0 .. gemm_num_configs() - 1).
+// Tuning ids of the fused GEMM (0 .. gemm_num_configs() - 1): 2 * tile
+// configuration + tile order.
 int gemm_num_configs();
 // Bytes of int64 carry space the GEMM needs when nkb > kb_chunk (valid for
 // every configuration).
 size_t gemm_flush_bytes(int S, int cfg, int num_cu);
 hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
+// One-wave-per-SIMD form of the fused GEMM (ozaki_gemm_w1.hip): single
+// problems without contraction chunking, S <= gemm_w1_max_slices(), tile
+// gemm_w1_tile_j() x gemm_w1_tile_i().
+int gemm_w1_max_slices();
+int64_t gemm_w1_tile_j();
+int64_t gemm_w1_tile_i();
+hipError_t launch_ozgemm_w1(int S, const GemmArgs &a, int num_cu, hipStream_t st);
 
 // Selector features and MLP (see ozaki_selector.hip).
 struct FeatTask {

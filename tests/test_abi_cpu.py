@@ -138,3 +138,35 @@ def test_probe_argument_errors():
     assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 5, 0, 1) == -13
     assert f("d", "N", "N", 2, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 0) == -15
     assert f("d", "N", "N", 0, 2, 2, 1, 2, 1, 2, 1, 2, 1, 0, 0) == 0
+
+
+def test_tuning_table_host_logic():
+    # The tuning table is host state: set / get / clear work without a GPU.
+    assert oz.ozaki_tune_clear() == 0
+    nid = oz.ozaki_tune_configs()
+    assert nid >= 2 and nid % 2 == 0
+    assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 7) == 0          # default id
+    assert oz.ozaki_tune_set("z", 2048, 2048, 2048, 7, nid - 1) == 0
+    assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 7) == nid - 1
+    # same buckets (ceil log2 of m, n', 32-deep blocks of k'): 1500 -> 11, 2n = 3000 -> 12
+    assert oz.ozaki_tune_get("z", 1500, 1500, 1500, 7) == nid - 1
+    assert oz.ozaki_tune_get("z", 2049, 2048, 2048, 7) == 0          # next m bucket
+    assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 6) == 0          # other slice count
+    assert oz.ozaki_tune_get("d", 2048, 4096, 4096, 7) == 0          # real data: own entries
+    assert oz.ozaki_tune_set("z", 2048, 2048, 2048, 7, -1) == 0      # remove
+    assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 7) == 0
+    assert oz.ozaki_tune_set("d", 64, 64, 64, 3, 1) == 0
+    assert oz.ozaki_tune_clear() == 0
+    assert oz.ozaki_tune_get("d", 64, 64, 64, 3) == 0
+    # argument errors
+    assert oz.ozaki_tune_set("q", 1, 1, 1, 7, 0) == -1
+    assert oz.ozaki_tune_set("d", 0, 1, 1, 7, 0) == -2
+    assert oz.ozaki_tune_set("d", 1, 0, 1, 7, 0) == -3
+    assert oz.ozaki_tune_set("d", 1, 1, 0, 7, 0) == -4
+    assert oz.ozaki_tune_set("d", 1, 1, 1, 13, 0) == -5
+    assert oz.ozaki_tune_set("d", 1, 1, 1, 7, nid) == -6
+    assert oz.ozaki_tune_get("z", 1, 1, 1, 0) == -5
+    rc, best, _ = oz.ozaki_autotune("d", 8, 8, 8, 7, reps=0)
+    assert rc == -6 and best == -1
+    assert oz.ozaki_autotune("x", 8, 8, 8, 7)[0] == -1
+    assert oz.ozaki_tune_save(None) == -1 and oz.ozaki_tune_load(None) == -1
