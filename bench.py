@@ -31,8 +31,10 @@ METRIC = "effective FP64 TFLOP/s, INT8-Ozaki ZGEMM vs native FP64 MFMA at ≤1e-
 INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 matrix peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
-GEMM_SOURCE = os.path.join(ROOT, "paper_2603_29975_amd", "csrc", "ozaki_gemm.hip")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_2603_29975_amd", "csrc", f)
+                for f in ("ozaki_gemm.hip", "ozaki_gemm_tile.hpp", "ozaki_gemm_w1.hip")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ozgemm_kkr2048_s7_traffic.txt")
+TUNE_CACHE = os.path.join(ROOT, "paper_2603_29975_amd", "tune_gfx950.json")
 
 
 def log(*a):
@@ -62,14 +64,19 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def source_hash(path: str) -> str:
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    """sha256 (first 16 hex digits) of the concatenated kernel sources."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic(per_launch_ops: float):
+def read_traffic(tune_id: int):
     """HBM bytes per launch of the fused GEMM kernel from the committed counter
-    summary, or None when it is missing or was taken on another kernel source."""
+    summary, or None when it is missing or was taken on another kernel source
+    or tuning id."""
     try:
         vals = {}
         with open(TRAFFIC_SUMMARY) as fh:
@@ -77,7 +84,9 @@ def read_traffic(per_launch_ops: float):
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCE):
+        if vals.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCES):
+            return None
+        if int(vals.get("tune_id", "0")) != tune_id:
             return None
         return float(vals["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -101,6 +110,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--tune", choices=["cache", "auto", "off"], default="cache",
+                    help="tile selection: the committed tuning table (autotune if it is "
+                         "missing), autotune now, or the default id")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -157,6 +169,7 @@ def main():
     int8_ops = pairs * flops                             # INT8 ops of the slice GEMM per call
 
     # ---------------------------------------------------------------- emulation
+    tuning = select_tiles(oz, args.tune, kind, m, n, k, s)
     for _ in range(args.warmup):
         run_ozaki()
     torch.cuda.synchronize()
@@ -179,11 +192,12 @@ def main():
 
     gemm_ms = phases["gemm"]
     achieved = int8_ops / (gemm_ms * 1e-3) / 1e12
-    traffic = read_traffic(int8_ops)
+    traffic = read_traffic(tuning["tune_id"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
                 "traffic": traffic,
-                "kernel": "k_ozgemm (fused INT8 slice-pair GEMM + FP64 recombination)",
+                "kernel": "fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
+                          f"{tuning['tune_id']})",
                 "ops_per_launch": int8_ops, "avg_launch_ms": round(gemm_ms, 4),
                 "note": "INT8 MFMA work counted as 2 ops per multiply-add against the "
                         "5000 TOP/s dense INT8 peak"}
@@ -241,9 +255,29 @@ def main():
         "speedup_vs_native": (round(native_rec["ms_per_call"] / ms_per_step, 3)
                               if native_rec else None),
         "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+        "tuning": tuning,
         "accuracy": accuracy,
     }
     print(json.dumps(out), flush=True)
+
+
+def select_tiles(oz, mode, kind, m, n, k, s):
+    """One-off tile selection for the workload shape, outside the timed region."""
+    oz.ozaki_tune_clear()
+    source = "default"
+    if mode == "cache" and os.path.exists(TUNE_CACHE):
+        rc = oz.ozaki_tune_load(TUNE_CACHE)
+        if rc != 0:
+            raise RuntimeError(f"ozaki_tune_load: {oz.ozaki_status_string(rc)}")
+        source = "cache"
+    if mode == "auto" or (mode == "cache" and source == "default"):
+        rc, _, _ = oz.ozaki_autotune(kind, m, n, k, s, reps=5)
+        if rc != 0:
+            raise RuntimeError(f"ozaki_autotune: {oz.ozaki_status_string(rc)}")
+        source = "autotune"
+    tid = oz.ozaki_tune_get(kind, m, n, k, s)
+    log(f"tiles: tuning id {tid} ({source})")
+    return {"tune_id": tid, "source": source, "ids": oz.ozaki_tune_configs()}
 
 
 def blas_threads() -> int:

@@ -169,11 +169,14 @@ int ozaki_batched_cache_clear(void);
  * OZAKI_TUNE_CACHE=<file> loads a saved table before the first lookup.
  * The batched path always uses id 0.
  *
- * ozaki_autotune: times every id on an m x n x k product with `slices` slices
- *   on the library's stream (zeroed operands in the library workspace, a
- *   temporary m x n output allocated and freed inside; the stream is
- *   synchronised), keeps the fastest in the table and returns it in *best and
- *   its time per launch in *best_ms (either may be NULL).
+ * ozaki_autotune: times the fused GEMM kernel of every id on an m x n x k
+ *   product with `slices` slices on the library's stream: packed operands of
+ *   pseudo-random digits in the library workspace (the kernel's clock depends
+ *   on its operand bits), a temporary m x n output allocated and freed inside,
+ *   one untimed round, then 5 rounds of `reps` launches per id round-robin; the
+ *   stream is synchronised. It keeps the id with the smallest median time per
+ *   launch in the table and returns it in *best and that time in *best_ms
+ *   (either may be NULL).
  *   Errors: kind -1 ('d' or 'z'), m -2, n -3, k -4 (each >= 1), slices -5,
  *   reps -6 (1..1000); OZAKI_ERR_* for device failures.
  * ozaki_tune_set: records `id` for the bucket of the shape (id < 0 removes the

@@ -1088,10 +1088,15 @@ int tune_save(const char *path) {
   return fclose(f) == 0 ? OZAKI_OK : OZAKI_ERR_IO;
 }
 
-// Times every tuning id of the fused GEMM on one shape (operands zeroed: the
-// kernel's time does not depend on the values) and records the fastest.
+// Times every tuning id of the fused GEMM on one shape and records the
+// fastest. The packed operands are filled with pseudo-random digits (the
+// kernel's power draw, and with it the clock, depends on the operand bits; all
+// zeros would time a faster chip), the exponent codes with e = 0. The ids are
+// timed round-robin, `reps` launches per id and round, after one untimed
+// round; an id's time is its median over the rounds.
 int autotune(bool cplx, int64_t m, int64_t n, int64_t k, int S, int reps, int *best,
              double *best_ms) {
+  constexpr int kRounds = 5;
   int dev = 0;
   int rc = current_device(&dev);
   if (rc) return rc;
@@ -1100,7 +1105,15 @@ int autotune(bool cplx, int64_t m, int64_t n, int64_t k, int S, int reps, int *b
   if ((rc = get_workspace(p.total, &wsv))) return rc;
   char *ws = static_cast<char *>(wsv);
   const hipStream_t st = g.stream;
-  if ((rc = hip_rc(launch_fill_i32(reinterpret_cast<int *>(ws), (int64_t)(p.total / 4), 0, st))))
+  if ((rc = hip_rc(launch_fill_i32(reinterpret_cast<int *>(ws + p.off_codeA), m, kCodeBias, st))))
+    return rc;
+  if ((rc = hip_rc(launch_fill_i32(reinterpret_cast<int *>(ws + p.off_codeB), n, kCodeBias, st))))
+    return rc;
+  if ((rc = hip_rc(launch_fill_digits(reinterpret_cast<int8_t *>(ws + p.off_SA),
+                                      (int64_t)(p.off_SB - p.off_SA), 0x5eed0001ull, st))))
+    return rc;
+  if ((rc = hip_rc(launch_fill_digits(reinterpret_cast<int8_t *>(ws + p.off_SB),
+                                      (int64_t)(p.off_flush - p.off_SB), 0x5eed0002ull, st))))
     return rc;
   void *C = nullptr;
   const size_t cbytes = (size_t)m * n * (cplx ? 16 : 8);
@@ -1108,38 +1121,39 @@ int autotune(bool cplx, int64_t m, int64_t n, int64_t k, int S, int reps, int *b
     (void)hipGetLastError();
     return OZAKI_ERR_ALLOC;
   }
+  const int nid = gemm_num_configs();
+  std::vector<std::vector<double>> t(nid);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = OZAKI_ERR_HIP;
   const GemmArgs ga = gemm_args(p, ws, 1.0, 0.0, 0.0, 0.0, true, C, m, nullptr);
-  int best_id = -1;
-  double best_t = 0.0;
-  for (int id = 0; rc == OZAKI_OK && id < gemm_num_configs(); ++id) {
-    double t_id = 0.0;
-    for (int trial = 0; rc == OZAKI_OK && trial < 3; ++trial) {
-      // trial 0 is a warm-up launch pair, trials 1 and 2 are timed
-      const int nl = trial == 0 ? 2 : reps;
+  for (int round = 0; rc == OZAKI_OK && round <= kRounds; ++round) {
+    for (int id = 0; rc == OZAKI_OK && id < nid; ++id) {
       if ((rc = hip_rc(hipEventRecord(e0, st)))) break;
-      for (int r = 0; rc == OZAKI_OK && r < nl; ++r)
+      for (int r = 0; rc == OZAKI_OK && r < reps; ++r)
         rc = hip_rc(launch_ozgemm(S, id, ga, g.dev[dev].num_cu, st));
       if (rc) break;
       if ((rc = hip_rc(hipEventRecord(e1, st)))) break;
       if ((rc = hip_rc(hipEventSynchronize(e1)))) break;
       float msf = 0.f;
       if ((rc = hip_rc(hipEventElapsedTime(&msf, e0, e1)))) break;
-      if (trial > 0) {
-        const double t = (double)msf / nl;
-        t_id = trial == 1 ? t : std::min(t_id, t);
-      }
-    }
-    if (rc == OZAKI_OK && (best_id < 0 || t_id < best_t)) {
-      best_id = id;
-      best_t = t_id;
+      if (round > 0) t[id].push_back((double)msf / reps);  // round 0 warms up
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (hipFree(C) != hipSuccess && rc == OZAKI_OK) rc = OZAKI_ERR_HIP;
   if (rc) return rc;
+  int best_id = 0;
+  double best_t = 0.0;
+  for (int id = 0; id < nid; ++id) {
+    std::vector<double> v = t[id];
+    std::sort(v.begin(), v.end());
+    const double med = v[v.size() / 2];
+    if (id == 0 || med < best_t) {
+      best_id = id;
+      best_t = med;
+    }
+  }
   g_tune[tune_key(cplx, S, m, p.nprime, p.nkb)] = TuneEntry{best_id, best_t};
   if (best) *best = best_id;
   if (best_ms) *best_ms = best_t;

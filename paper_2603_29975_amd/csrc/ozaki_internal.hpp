@@ -9,6 +9,8 @@ namespace oz {
 // Exponent step: code[r] = max over row r of expo_code (code must hold zeros
 // on entry; launch_fill_i32 provides them).
 hipError_t launch_fill_i32(int *p, int64_t n, int value, hipStream_t st);
+// Pseudo-random digits in [-127, 127] (timing data of the autotuner).
+hipError_t launch_fill_digits(int8_t *p, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st);
 
 // Slicing step: writes all nrb*32 x nkb*32 packed rows/entries of S slices.
