@@ -289,7 +289,8 @@ size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int sli
 int ozaki_timing_enable(int on);
 int ozaki_timing_read(double *ms, int64_t *calls);
 
-/* Release the library's own device buffer (safe to call more than once). */
+/* Release the library's own device buffers: the workspace and the scratch of
+ * the automatic slice mode (safe to call more than once). */
 int ozaki_finalize(void);
 
 /* Static text for a status code. */

@@ -448,6 +448,7 @@ struct BatchedPlan {
   std::vector<uint8_t> sig;  // exact argument signature
   int dev = 0;
   void *mem = nullptr;
+  bool owns_mem = true;  // false: mem belongs to a caller's buffer
   size_t off_probs = 0, off_scan = 0, off_scan_start = 0, off_split = 0, off_split_start = 0,
          off_flush = 0;
   int nscan = 0, nsplit = 0;
@@ -471,7 +472,7 @@ void free_plan(BatchedPlan *pl) {
   if (pl == nullptr) return;
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
-  if (pl->mem) {
+  if (pl->mem && pl->owns_mem) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(pl->dev);
@@ -526,48 +527,19 @@ int enqueue_plan(const BatchedPlan &pl, hipStream_t st, bool capturing) {
 }
 
 // Builds (or finds) the plan of a validated batched call.
-int get_plan(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
-             const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A, const int64_t *lda,
-             const ozaki_z *const *B, const int64_t *ldb, const ozaki_z *beta, ozaki_z *const *C,
-             const int64_t *ldc, int64_t batch, const int *slices, BatchedPlan **out) {
-  int dev = 0;
-  int rc = current_device(&dev);
-  if (rc) return rc;
-  std::vector<uint8_t> sig;
-  sig_put(sig, dev);
-  sig_put(sig, batch);
-  for (int64_t b = 0; b < batch; ++b) {
-    sig_put(sig, up(transa[b]));
-    sig_put(sig, up(transb[b]));
-    sig_put(sig, m[b]);
-    sig_put(sig, n[b]);
-    sig_put(sig, k[b]);
-    sig_put(sig, alpha[b]);
-    sig_put(sig, A[b]);
-    sig_put(sig, lda[b]);
-    sig_put(sig, B[b]);
-    sig_put(sig, ldb[b]);
-    sig_put(sig, beta[b]);
-    sig_put(sig, C[b]);
-    sig_put(sig, ldc[b]);
-    sig_put(sig, slices[b]);
-  }
-  for (auto it = g_bat.cache.begin(); it != g_bat.cache.end(); ++it) {
-    if ((*it)->sig == sig) {
-      BatchedPlan *pl = *it;
-      g_bat.cache.erase(it);
-      g_bat.cache.push_front(pl);
-      *out = pl;
-      return OZAKI_OK;
-    }
-  }
-
-  BatchedPlan *pl = new BatchedPlan();
-  pl->sig = std::move(sig);
-  pl->dev = dev;
+// Lays out one batched plan: problem descriptors, scan and split task tables,
+// tile tables (one group per slice count, longest contraction first) and the
+// workspace of every emulated problem. alloc(total) provides the device memory
+// (nullptr on failure); the descriptor tables are returned in `host`, to be
+// copied to the start of that memory by the caller.
+template <typename Alloc>
+int build_plan(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+               const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A,
+               const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
+               const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
+               const int *slices, int num_cu, BatchedPlan *pl, Alloc alloc,
+               std::vector<uint8_t> &host) {
   pl->used.assign((size_t)batch, 0);
-  const int num_cu = g.dev[dev].num_cu;
-
   std::vector<GemmProblem> probs;
   std::vector<ScanTask> scans;
   std::vector<SplitTask> splits;
@@ -645,12 +617,9 @@ int get_plan(const char *transa, const char *transb, const int64_t *m, const int
   const size_t off_ws = take(ws_total);
   const size_t total = off;
 
-  if (hipMalloc(&pl->mem, total) != hipSuccess) {
-    (void)hipGetLastError();
-    free_plan(pl);
-    return OZAKI_ERR_ALLOC;
-  }
-  char *base = static_cast<char *>(pl->mem);
+  char *base = alloc(total);
+  if (base == nullptr) return OZAKI_ERR_ALLOC;
+  pl->mem = base;
 
   // patch device pointers into the descriptors
   for (size_t i = 0; i < np; ++i) {
@@ -668,7 +637,7 @@ int get_plan(const char *transa, const char *transb, const int64_t *m, const int
     splits[2 * i + 1].code = reinterpret_cast<const int *>(w + p.off_codeB);
     splits[2 * i + 1].out = reinterpret_cast<int8_t *>(w + p.off_SB);
   }
-  std::vector<uint8_t> host(desc_bytes, 0);
+  host.assign(desc_bytes, 0);
   auto put = [&](size_t o, const void *src, size_t bytes) {
     if (bytes) std::memcpy(host.data() + o, src, bytes);
   };
@@ -694,7 +663,66 @@ int get_plan(const char *transa, const char *transb, const int64_t *m, const int
     put(pl->groups[gi].off_tile_local, tl.data(), tl.size() * sizeof(int));
     ++gi;
   }
-  if (hipMemcpy(pl->mem, host.data(), desc_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+  return OZAKI_OK;
+}
+
+int get_plan(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
+             const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A, const int64_t *lda,
+             const ozaki_z *const *B, const int64_t *ldb, const ozaki_z *beta, ozaki_z *const *C,
+             const int64_t *ldc, int64_t batch, const int *slices, BatchedPlan **out) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::vector<uint8_t> sig;
+  sig_put(sig, dev);
+  sig_put(sig, batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    sig_put(sig, up(transa[b]));
+    sig_put(sig, up(transb[b]));
+    sig_put(sig, m[b]);
+    sig_put(sig, n[b]);
+    sig_put(sig, k[b]);
+    sig_put(sig, alpha[b]);
+    sig_put(sig, A[b]);
+    sig_put(sig, lda[b]);
+    sig_put(sig, B[b]);
+    sig_put(sig, ldb[b]);
+    sig_put(sig, beta[b]);
+    sig_put(sig, C[b]);
+    sig_put(sig, ldc[b]);
+    sig_put(sig, slices[b]);
+  }
+  for (auto it = g_bat.cache.begin(); it != g_bat.cache.end(); ++it) {
+    if ((*it)->sig == sig) {
+      BatchedPlan *pl = *it;
+      g_bat.cache.erase(it);
+      g_bat.cache.push_front(pl);
+      *out = pl;
+      return OZAKI_OK;
+    }
+  }
+
+  BatchedPlan *pl = new BatchedPlan();
+  pl->sig = std::move(sig);
+  pl->dev = dev;
+  std::vector<uint8_t> host;
+  rc = build_plan(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, slices,
+                  g.dev[dev].num_cu, pl,
+                  [](size_t bytes) -> char * {
+                    void *p = nullptr;
+                    if (hipMalloc(&p, bytes) != hipSuccess) {
+                      (void)hipGetLastError();
+                      return nullptr;
+                    }
+                    return static_cast<char *>(p);
+                  },
+                  host);
+  if (rc) {
+    free_plan(pl);
+    return rc;
+  }
+
+  if (hipMemcpy(pl->mem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_plan(pl);
     return OZAKI_ERR_HIP;
   }
@@ -753,8 +781,30 @@ struct SelectorState {
   double kappa = 8.0;     // probe estimate times kappa must meet the target
   void *ws = nullptr;     // grow-only scratch of the automatic mode
   size_t ws_bytes = 0;
+  void *plan_ws = nullptr;  // grow-only memory of the per-round batched plans
+  size_t plan_ws_bytes = 0;
 };
 SelectorState g_sel;
+
+// Memory for one round's batched plan in the automatic mode (grow-only; the
+// previous round's work is complete before the next plan is laid out).
+char *sel_plan_memory(size_t bytes) {
+  if (g_sel.plan_ws_bytes < bytes) {
+    if (g_sel.plan_ws != nullptr) {
+      (void)hipFree(g_sel.plan_ws);
+      g_sel.plan_ws = nullptr;
+      g_sel.plan_ws_bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_sel.plan_ws = p;
+    g_sel.plan_ws_bytes = bytes;
+  }
+  return static_cast<char *>(g_sel.plan_ws);
+}
 
 int load_selector(const float *params, float margin, double target, double kappa) {
   if (params == nullptr) return -1;
@@ -846,7 +896,7 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     o_codeA[e] = take(sizeof(int) * m[b]);
     o_codeB[e] = take(sizeof(int) * n[b]);
     o_P[e] = take(sizeof(ozaki_z) * m[b] * n[b]);
-    o_w[e] = take(probe_workspace_bytes(k[b]));
+    o_w[e] = take(probe_workspace_bytes(m[b], n[b], k[b]));
     o_est[e] = take(sizeof(double) * m[b]);
     sum_m += m[b];
   }
@@ -854,9 +904,9 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
                o_feat = take(sizeof(float) * 64 * ne), o_y = take(sizeof(float) * ne),
                o_scan = take(sizeof(ScanTask) * 2 * ne), o_scan_s = take(sizeof(int64_t) * (2 * ne + 1)),
                o_ft = take(sizeof(FeatTask) * 2 * ne), o_ft_s = take(sizeof(int64_t) * (2 * ne + 1)),
-               o_pt = take(sizeof(ProbeTask) * ne), o_pt_k = take(sizeof(int64_t) * (ne + 1)),
-               o_pt_m = take(sizeof(int64_t) * (ne + 1)), o_ax = take(sizeof(AxpbyTask) * ne),
-               o_ax_s = take(sizeof(int64_t) * (ne + 1)), o_mlp = take(mlp_scratch_bytes(ne));
+               o_pt = take(sizeof(ProbeTask) * ne), o_ax = take(sizeof(AxpbyTask) * ne),
+               o_ax_s = take(sizeof(int64_t) * (ne + 1)), o_mlp = take(mlp_scratch_bytes(ne)),
+               o_emax = take(sizeof(double) * ne);
   char *ws = nullptr;
   if ((rc = auto_ws(off, &ws))) return rc;
 
@@ -929,7 +979,7 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     std::vector<ozaki_z *> pc(np);
     std::vector<int> sl(np);
     std::vector<ProbeTask> pts(np);
-    std::vector<int64_t> sk(np + 1, 0), sm(np + 1, 0);
+    int64_t nblk[4] = {0, 0, 0, 0};
     for (size_t x = 0; x < np; ++x) {
       const int64_t e = pending[x], b = E[e];
       ta[x] = transa[b];
@@ -945,49 +995,46 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
       pc[x] = reinterpret_cast<ozaki_z *>(ws + o_P[e]);
       sl[x] = s_of[e];
       ProbeTask &pt = pts[x];
-      pt.va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
-      pt.vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
-      pt.C = pc[x];
-      pt.ldc = m[b];
-      pt.cplx = 1;
-      pt.nv = 2;
-      pt.seed = 0x5eed0000ull + (uint64_t)round;
-      pt.w = reinterpret_cast<double *>(ws + o_w[e]);
-      pt.ub = pt.w + (size_t)k[b] * 16;
-      pt.est = reinterpret_cast<double *>(ws + o_est[e]);
-      sk[x + 1] = sk[x] + probe_task_blocks_k(pt);
-      sm[x + 1] = sm[x] + probe_task_blocks_m(pt);
+      pt = probe_task(view_opA(A[b], transa[b], m[b], k[b], lda[b], true),
+                      view_opB(B[b], transb[b], k[b], n[b], ldb[b], true), true, pc[x], m[b], 2,
+                      0x5eed0000ull + (uint64_t)round, ws + o_w[e],
+                      reinterpret_cast<double *>(ws + o_est[e]));
+      for (int stage = 0; stage < 4; ++stage) {
+        pt.blk[stage] = nblk[stage];
+        nblk[stage] += probe_stage_blocks(pt, stage);
+      }
     }
-    if ((rc = run_fixed_batched(ta.data(), tb.data(), mm.data(), nn.data(), kk.data(), one.data(),
-                                pa.data(), la.data(), pb.data(), lb.data(), zero.data(), pc.data(),
-                                lc.data(), (int64_t)np, sl.data())))
+    // this round's products with alpha = 1, beta = 0 into P: a one-off plan in
+    // the automatic mode's own memory, launched directly (no cache, no graph)
+    BatchedPlan rp;
+    rp.dev = dev;
+    rp.owns_mem = false;
+    std::vector<uint8_t> host;
+    if ((rc = build_plan(ta.data(), tb.data(), mm.data(), nn.data(), kk.data(), one.data(), pa.data(),
+                         la.data(), pb.data(), lb.data(), zero.data(), pc.data(), lc.data(),
+                         (int64_t)np, sl.data(), g.dev[dev].num_cu, &rp, sel_plan_memory, host)))
       return rc;
+    if ((rc = hip_rc(hipMemcpyAsync(rp.mem, host.data(), host.size(), hipMemcpyHostToDevice, st))))
+      return rc;
+    if ((rc = enqueue_plan(rp, st, false))) return rc;
     if ((rc = h2d(o_pt, pts.data(), np * sizeof(ProbeTask)))) return rc;
-    if ((rc = h2d(o_pt_k, sk.data(), (np + 1) * sizeof(int64_t)))) return rc;
-    if ((rc = h2d(o_pt_m, sm.data(), (np + 1) * sizeof(int64_t)))) return rc;
-    if ((rc = hip_rc(launch_probe_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt),
-                                          reinterpret_cast<const int64_t *>(ws + o_pt_k), sk.back(),
-                                          reinterpret_cast<const int64_t *>(ws + o_pt_m), sm.back(),
-                                          (int)np, st))))
+    if ((rc = hip_rc(launch_probe_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt), (int)np,
+                                          nblk, st))))
       return rc;
-    std::vector<std::vector<double>> est(np);
-    for (size_t x = 0; x < np; ++x) {
-      est[x].resize(mm[x]);
-      if ((rc = hip_rc(hipMemcpyAsync(est[x].data(), ws + o_est[pending[x]], sizeof(double) * mm[x],
-                                      hipMemcpyDeviceToHost, st))))
-        return rc;
-    }
+    if ((rc = hip_rc(launch_probe_max_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt), (int)np,
+                                              reinterpret_cast<double *>(ws + o_emax), st))))
+      return rc;
+    std::vector<double> emax(np);
+    if ((rc = hip_rc(hipMemcpyAsync(emax.data(), ws + o_emax, sizeof(double) * np,
+                                    hipMemcpyDeviceToHost, st))))
+      return rc;
+    // also keeps `host` and the task vectors alive until their copies are done
     if ((rc = hip_rc(hipStreamSynchronize(st)))) return rc;
     std::vector<int64_t> next;
     for (size_t x = 0; x < np; ++x) {
-      double mx = 0.0;
-      bool bad = false;
-      for (double v : est[x]) {
-        if (std::isnan(v)) bad = true;  // non-finite inputs: NaN rows, nothing to raise
-        else mx = std::max(mx, v);
-      }
+      const double mx = emax[x];  // NaN: non-finite inputs, NaN rows, nothing to raise
       const int64_t e = pending[x];
-      if (!bad && mx * g_sel.kappa > g_sel.target && s_of[e] < OZAKI_S_MAX) {
+      if (!std::isnan(mx) && mx * g_sel.kappa > g_sel.target && s_of[e] < OZAKI_S_MAX) {
         ++s_of[e];
         next.push_back(e);
       }
@@ -1334,10 +1381,10 @@ int ozaki_probe(char kind, char transa, char transb, int64_t m, int64_t n, int64
   if (k > 0 && A == nullptr) return -7;
   if (k > 0 && n > 0 && B == nullptr) return -9;
   void *wsv = nullptr;
-  if ((rc = get_workspace(probe_workspace_bytes(k), &wsv))) return rc;
+  if ((rc = get_workspace(probe_workspace_bytes(m, n, k), &wsv))) return rc;
   const View va = view_opA(A, transa, m, k, lda, cplx);
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
-  return hip_rc(launch_probe(va, vb, cplx, C, ldc, m, n, k, nvec, seed, wsv, est, g.stream));
+  return hip_rc(launch_probe(va, vb, cplx, C, ldc, nvec, seed, wsv, est, g.stream));
 }
 
 int ozaki_features(char kind, char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -1501,6 +1548,17 @@ int ozaki_finalize(void) {
       g.own_ws_bytes[d] = 0;
     }
   }
+  // scratch of the automatic slice mode (the selector itself stays loaded)
+  for (void **p : {&g_sel.ws, &g_sel.plan_ws}) {
+    if (*p == nullptr) continue;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) rc = OZAKI_ERR_HIP;
+    if (hipSetDevice(g_sel.dev) != hipSuccess || hipFree(*p) != hipSuccess) rc = OZAKI_ERR_HIP;
+    (void)hipSetDevice(cur);
+    *p = nullptr;
+  }
+  g_sel.ws_bytes = 0;
+  g_sel.plan_ws_bytes = 0;
   return rc;
 }
 

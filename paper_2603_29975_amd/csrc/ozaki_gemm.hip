@@ -58,7 +58,8 @@ using tile::barrier_only;
 using tile::chunk_blocks;
 using tile::wait_vmcnt;
 
-template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED>
+template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED,
+          bool EARLY>
 __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
   __shared__ __attribute__((aligned(16))) int8_t lds[C_::LDS];
@@ -98,10 +99,7 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
           const int p = g / C_::NQB, rb = g % C_::NQB;
           src = a.SQ + (((int64_t)p * a.nrbQ + ti * C_::NQB + rb) * nkb + kb) * kFragBytes;
         }
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(src + lane * 16),
-            (__attribute__((address_space(3))) void *)(lds + buf * C_::STAGE + f * kFragBytes), 16,
-            0, 0);
+        tile::copy_frag(src + lane * 16, lds + buf * C_::STAGE + f * kFragBytes);
       }
     };
 
@@ -146,20 +144,39 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
         issue(kb + D, nb);
       }
       const int8_t *L = lds + buf * C_::STAGE;
-      v4i pf[S];
+      // All fragment reads of the block are issued up front, A' of slice 1
+      // first; a wave's LDS reads return in order, so each MFMA waits only for
+      // the reads it needs and the later ones arrive under the earlier MFMAs.
+      v4i qf[S][IB];
 #pragma unroll
-      for (int q = 0; q < S; ++q)
+      for (int ib = 0; ib < IB; ++ib)
+        qf[0][ib] = *reinterpret_cast<const v4i *>(
+            L + (C_::NFP + wi * IB + ib) * kFragBytes + lane * 16);
+      // The compiler starts each block with the MFMA of the longest
+      // accumulation chain (slice pair 1, S), so B' slice S is read second.
+      v4i pf[S];
+      pf[S - 1] = *reinterpret_cast<const v4i *>(L + ((S - 1) * WJ + wj) * kFragBytes + lane * 16);
+#pragma unroll
+      for (int q = 0; q < S - 1; ++q)
         pf[q] = *reinterpret_cast<const v4i *>(L + (q * WJ + wj) * kFragBytes + lane * 16);
+#pragma unroll
+      for (int p = 1; p < S; ++p)
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib)
+          qf[p][ib] = *reinterpret_cast<const v4i *>(
+              L + (C_::NFP + p * C_::NQB + wi * IB + ib) * kFragBytes + lane * 16);
+      // EARLY keeps the reads above the MFMAs (the scheduler would otherwise
+      // sink each A' read to just before its first use and expose its
+      // latency); for large S the registers of all fragments would not fit
+      if constexpr (EARLY && S * (1 + IB) <= 18) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int p = 0; p < S; ++p) {
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
-          const v4i qf = *reinterpret_cast<const v4i *>(
-              L + (C_::NFP + p * C_::NQB + wi * IB + ib) * kFragBytes + lane * 16);
 #pragma unroll
           for (int q = 0; q < S - p; ++q)
             acc[ib][p + q] =
-                __builtin_amdgcn_mfma_i32_32x32x32_i8(pf[q], qf, acc[ib][p + q], 0, 0, 0);
+                __builtin_amdgcn_mfma_i32_32x32x32_i8(pf[q], qf[p][ib], acc[ib][p + q], 0, 0, 0);
         }
       }
       if constexpr (chunked) {
@@ -186,7 +203,7 @@ __global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
   }
 }
 
-template <int S, int WJ, int WI, int IB, int NBUF, bool WITH_RAW>
+template <int S, int WJ, int WI, int IB, int NBUF, bool WITH_RAW, bool EARLY = false>
 hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
   const bool grouped = a.probs != nullptr;
@@ -199,23 +216,23 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   const dim3 g((unsigned)grid), b(C_::NT);
   if (grouped) {
     if (a.chunked)
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, true>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, true, EARLY>), g, b, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, true>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, true, EARLY>), g, b, 0, st, a);
   } else if (a.one.raw != nullptr) {
     if constexpr (WITH_RAW) {
       if (a.chunked)
-        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true, false>), g, b, 0, st, a);
+        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, true, false, EARLY>), g, b, 0, st, a);
       else
-        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false, false>), g, b, 0, st, a);
+        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, true, false, false, EARLY>), g, b, 0, st, a);
     } else {
       return hipErrorInvalidValue;
     }
   } else {
     if (a.chunked)
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, false, EARLY>), g, b, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, false>), g, b, 0, st, a);
+      hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, false, EARLY>), g, b, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -230,9 +247,10 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //   3: the one-wave-per-SIMD kernel of ozaki_gemm_w1.hip (same 128 j' x 64 i
 //      tile, two blocks per wave, fragments double-buffered in registers) for
 //      S <= 8 without contraction chunking; configuration 0 otherwise
+//   4: as 2 with every fragment read of a block issued before its MFMAs
 // A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
 // down the rows i, 1: along the columns j').
-constexpr int kNumCfg = 4;
+constexpr int kNumCfg = 5;
 
 template <int CFG>
 struct Pick;
@@ -270,6 +288,7 @@ hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
       if (S <= gemm_w1_max_slices() && a.probs == nullptr && a.one.raw == nullptr && !a.chunked)
         return launch_ozgemm_w1(S, a, num_cu, st);
       return launch_pick<S, 0>(a, num_cu, st);
+    case 4: return launch_cfg<S, 4, 2, 1, 2, false, true>(a, num_cu, st);
     default: return launch_pick<S, 0>(a, num_cu, st);
   }
 }
@@ -300,6 +319,7 @@ int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
     case 1: BJ = 32 * Pick<1>::WJ; BI = 32 * Pick<1>::WI * Pick<1>::IB; break;
     case 2: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
     case 3: BJ = gemm_w1_tile_j(); BI = gemm_w1_tile_i(); break;
+    case 4: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
     default: BJ = 32 * Pick<0>::WJ; BI = 32 * Pick<0>::WI * Pick<0>::IB; break;
   }
   return ((nprime + BJ - 1) / BJ) * ((m + BI - 1) / BI);

@@ -24,6 +24,24 @@ __device__ __forceinline__ void wait_vmcnt() {
 __device__ __forceinline__ void wait_lgkm0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
 
+// One 1 KiB slice fragment from global memory straight into LDS: lane l
+// copies the 16 bytes at src_lane (its own part of the fragment) to LDS
+// address lds_wave + 16 l. Inline assembly rather than the compiler's builtin
+// for the same instruction: with the builtin in a loop the compiler waits for
+// every outstanding LDS read (lgkmcnt(0)) before each fragment's first use,
+// which serialises the fragment reads with the MFMAs; with the copy hidden
+// from it, it waits for exactly the reads each MFMA needs. The copy counts in
+// vmcnt, which the kernels wait on explicitly (wait_vmcnt); the LDS base goes
+// through M0, set in the same statement.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void copy_frag(const int8_t *src_lane, const int8_t *lds_wave) {
+  const uint32_t la = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) int8_t *)lds_wave;
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src_lane), "s"(la)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
 // Contraction blocks of 32 a chunk may hold: S * 32 * kb * 127^2 <= 2^31 - 1.
 __host__ __device__ constexpr int64_t chunk_blocks(int S) {
   return (int64_t)(2147483647ll / ((int64_t)S * 32 * 127 * 127));

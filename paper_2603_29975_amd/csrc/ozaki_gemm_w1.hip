@@ -112,10 +112,7 @@ k_ozgemm_w1(GemmArgs G) {
           const int p = g / C_::WI, rb = g % C_::WI;
           src = a.SQ + (((int64_t)p * a.nrbQ + ti * C_::WI + rb) * nkb + kb) * kFragBytes;
         }
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(src + lane * 16),
-            (__attribute__((address_space(3))) void *)(lds + buf * C_::STAGE + f * kFragBytes), 16,
-            0, 0);
+        tile::copy_frag(src + lane * 16, lds + buf * C_::STAGE + f * kFragBytes);
       }
     };
     auto read = [&](int buf, Frags<S> &F) {

@@ -137,8 +137,9 @@ hipError_t mlp_backward(void *state, int64_t b, const float *y, const float *tar
 hipError_t mlp_adam(void *state, float lr, float b1, float b2, float eps, int64_t step,
                     hipStream_t st);
 
-// Randomized residual probe (see ozaki_probe.hip). A batched task probes one
-// product: w and ub are its scratch (k * 17 doubles), est receives m values.
+// Randomized residual probe (see ozaki_probe.hip). A task probes one product
+// in four stages over chunks of its contraction (chl) and columns (chj); its
+// scratch (w, ub and the chunk records p1, p2) comes from probe_task.
 struct ProbeTask {
   View va, vb;
   const void *C;
@@ -146,7 +147,9 @@ struct ProbeTask {
   int cplx;
   int nv;
   uint64_t seed;
-  double *w, *ub, *est;
+  double *w, *ub, *est, *p1, *p2;
+  int64_t chl, chj, ncl, ncj;
+  int64_t blk[4];  // batched: first block of this task in each stage
 };
 // C = alpha P + beta C over complex problems (P: m x n, leading dimension m).
 struct AxpbyTask {
@@ -156,18 +159,23 @@ struct AxpbyTask {
   double ar, ai, br, bi;
   int beta_zero;
 };
-int64_t probe_task_blocks_k(const ProbeTask &t);
-int64_t probe_task_blocks_m(const ProbeTask &t);
 int64_t axpby_task_blocks(const AxpbyTask &t);
-hipError_t launch_probe_batched(const ProbeTask *tasks, const int64_t *start_k, int64_t nblk_k,
-                                const int64_t *start_m, int64_t nblk_m, int ntasks, hipStream_t st);
+// Scratch bytes of one probe, its task (scratch at ws), blocks per stage, and
+// the launches: one task, or a table of tasks whose blk[] hold the prefix sums
+// of probe_stage_blocks (nblk[s] blocks in stage s).
+size_t probe_workspace_bytes(int64_t m, int64_t n, int64_t k);
+ProbeTask probe_task(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc, int nv,
+                     uint64_t seed, void *ws, double *est);
+int64_t probe_stage_blocks(const ProbeTask &t, int stage);
+hipError_t launch_probe_batched(const ProbeTask *tasks, int ntasks, const int64_t *nblk,
+                                hipStream_t st);
 hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, int ntasks,
                                 int64_t nblocks, hipStream_t st);
-size_t probe_workspace_bytes(int64_t k);
 int probe_max_vectors();
+hipError_t launch_probe_max_batched(const ProbeTask *tasks, int ntasks, double *out,
+                                    hipStream_t st);
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
-                        int64_t m, int64_t n, int64_t k, int nv, uint64_t seed, void *ws, double *est,
-                        hipStream_t st);
+                        int nv, uint64_t seed, void *ws, double *est, hipStream_t st);
 
 // Native FP64 matrix-core GEMM.
 struct NativeArgs {

@@ -18,6 +18,8 @@
 // Sign vectors: x_v[j] = +1 or -1 by the top bit of SplitMix64(seed + v*n + j)
 // (Steele, Lea and Flood 2014; the finalizer constants of Vigna's published
 // splitmix64).
+#include <algorithm>
+
 #include "ozaki_internal.hpp"
 
 namespace oz {
@@ -74,86 +76,138 @@ __device__ __forceinline__ double2 ld(const View &v, int64_t r, int64_t l) {
   return make_double2(reinterpret_cast<const double *>(v.base)[r * v.sr + l * v.sl], 0.0);
 }
 
-// w_v[l] = sum_j op(B)(l, j) x_v[j] and ub[l] = sum_j |op(B)(l, j)|, one thread
-// per l. vb views op(B) with rows = columns j and contraction = l, so
-// op(B)(l, j) = vb(j, l). Output per l: [v][re.hi, re.lo, im.hi, im.lo].
+// The sums run in chunks so that a problem spreads over many threads (one
+// thread per output and chunk, each chunk's compensated sum written out as a
+// partial record, then one thread per output adding the records in chunk
+// order): a thread per output alone would leave the GPU mostly idle behind
+// k + n long dependent chains. A record holds, for every vector v, the two
+// compensated sums (re.hi, re.lo, im.hi, im.lo) and one plain sum.
+constexpr int kRec = kMaxVec * 4 + 1;
+
+__device__ __forceinline__ void put_rec(double *o, const Dd *re, const Dd *im, int nv, double u) {
+  for (int v = 0; v < nv; ++v) {
+    o[v * 4 + 0] = re[v].hi;
+    o[v * 4 + 1] = re[v].lo;
+    o[v * 4 + 2] = im[v].hi;
+    o[v * 4 + 3] = im[v].lo;
+  }
+  o[kMaxVec * 4] = u;
+}
+
+__device__ __forceinline__ void add_rec(const double *o, Dd *re, Dd *im, int nv, double &u) {
+  for (int v = 0; v < nv; ++v) {
+    acc_add(re[v], o[v * 4 + 0]);
+    re[v].lo = add_rn(re[v].lo, o[v * 4 + 1]);
+    acc_add(im[v], o[v * 4 + 2]);
+    im[v].lo = add_rn(im[v].lo, o[v * 4 + 3]);
+  }
+  u = add_rn(u, o[kMaxVec * 4]);
+}
+
+// Stage 1, thread (l, chunk c of columns j): partial w_v[l] = sum_j op(B)(l, j)
+// x_v[j] and ub[l] = sum_j |op(B)(l, j)|. vb views op(B) with rows = columns
+// j and contraction = l, so op(B)(l, j) = vb(j, l).
 template <bool CPLX>
-__device__ void probe_bx(const View &vb, int nv, uint64_t seed, double *w, double *ub, int64_t l) {
-  const int64_t K = vb.L, N = vb.R;
-  if (l >= K) return;
+__device__ void bx_part(const ProbeTask &tk, int64_t idx) {
+  const int64_t K = tk.vb.L, N = tk.vb.R;
+  if (idx >= K * tk.ncj) return;
+  const int64_t l = idx % K, c = idx / K;
+  const int64_t j0 = c * tk.chj, j1 = j0 + tk.chj < N ? j0 + tk.chj : N;
   Dd re[kMaxVec], im[kMaxVec];
   double u = 0.0;
-  for (int64_t j = 0; j < N; ++j) {
-    const double2 b = ld<CPLX>(vb, j, l);
+  for (int64_t j = j0; j < j1; ++j) {
+    const double2 b = ld<CPLX>(tk.vb, j, l);
     u = add_rn(u, CPLX ? hypot(b.x, b.y) : fabs(b.x));
-    for (int v = 0; v < nv; ++v) {
-      const double s = sign_of(seed, v, N, j);
+    for (int v = 0; v < tk.nv; ++v) {
+      const double s = sign_of(tk.seed, v, N, j);
       acc_add(re[v], mul_rn(s, b.x));
       if (CPLX) acc_add(im[v], mul_rn(s, b.y));
     }
   }
-  for (int v = 0; v < nv; ++v) {
-    double *o = w + (l * kMaxVec + v) * 4;
+  put_rec(tk.p1 + (c * K + l) * kRec, re, im, tk.nv, u);
+}
+
+// Stage 2, thread l: w[l] (per v: re.hi, re.lo, im.hi, im.lo) and ub[l] from
+// the chunk records in order.
+__device__ void bx_sum(const ProbeTask &tk, int64_t l) {
+  const int64_t K = tk.vb.L;
+  if (l >= K) return;
+  Dd re[kMaxVec], im[kMaxVec];
+  double u = 0.0;
+  for (int64_t c = 0; c < tk.ncj; ++c) add_rec(tk.p1 + (c * K + l) * kRec, re, im, tk.nv, u);
+  for (int v = 0; v < tk.nv; ++v) {
+    double *o = tk.w + (l * kMaxVec + v) * 4;
     o[0] = re[v].hi;
     o[1] = re[v].lo;
     o[2] = im[v].hi;
     o[3] = im[v].lo;
   }
-  ub[l] = u;
+  tk.ub[l] = u;
 }
 
+// Stage 3, thread (i, chunk c): for c < ncl the partial z_v = sum_l op(A)(i, l)
+// w_v[l] (w as hi + lo) and u = sum_l |op(A)(i, l)| ub[l] over a chunk of l;
+// for c >= ncl the partial y_v = sum_j C(i, j) x_v[j] over a chunk of j.
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_probe_bx(View vb, int nv, uint64_t seed, double *w,
-                                                  double *ub) {
-  probe_bx<CPLX>(vb, nv, seed, w, ub, (int64_t)blockIdx.x * 256 + threadIdx.x);
-}
-
-// Per row i: z_v = sum_l op(A)(i, l) w_v[l] (w as hi + lo), y_v = sum_j C(i, j)
-// x_v[j], u = sum_l |op(A)(i, l)| ub[l]; est[i] as described above.
-template <bool CPLX>
-__device__ void probe_rows(const View &va, const void *C, int64_t ldc, int64_t n, int nv,
-                           uint64_t seed, const double *w, const double *ub, double *est,
-                           int64_t i) {
-  const int64_t M = va.R, K = va.L;
-  if (i >= M) return;
-  Dd zr[kMaxVec], zi[kMaxVec], yr[kMaxVec], yi[kMaxVec];
+__device__ void rows_part(const ProbeTask &tk, int64_t idx) {
+  const int64_t M = tk.va.R, K = tk.va.L, N = tk.vb.R;
+  if (idx >= M * (tk.ncl + tk.ncj)) return;
+  const int64_t i = idx % M, c = idx / M;
+  Dd xr[kMaxVec], xi[kMaxVec];
   double u = 0.0;
-  for (int64_t l = 0; l < K; ++l) {
-    const double2 a = ld<CPLX>(va, i, l);
-    u = add_rn(u, mul_rn(CPLX ? hypot(a.x, a.y) : fabs(a.x), ub[l]));
-    for (int v = 0; v < nv; ++v) {
-      const double *o = w + (l * kMaxVec + v) * 4;
-      // (ar + i ai)(wr + i wi) with w = hi + lo in both parts
-      acc_mac(zr[v], a.x, o[0]);
-      acc_mac(zr[v], a.x, o[1]);
+  if (c < tk.ncl) {
+    const int64_t l0 = c * tk.chl, l1 = l0 + tk.chl < K ? l0 + tk.chl : K;
+    for (int64_t l = l0; l < l1; ++l) {
+      const double2 a = ld<CPLX>(tk.va, i, l);
+      u = add_rn(u, mul_rn(CPLX ? hypot(a.x, a.y) : fabs(a.x), tk.ub[l]));
+      for (int v = 0; v < tk.nv; ++v) {
+        const double *o = tk.w + (l * kMaxVec + v) * 4;
+        // (ar + i ai)(wr + i wi) with w = hi + lo in both parts
+        acc_mac(xr[v], a.x, o[0]);
+        acc_mac(xr[v], a.x, o[1]);
+        if (CPLX) {
+          acc_mac(xr[v], -a.y, o[2]);
+          acc_mac(xr[v], -a.y, o[3]);
+          acc_mac(xi[v], a.x, o[2]);
+          acc_mac(xi[v], a.x, o[3]);
+          acc_mac(xi[v], a.y, o[0]);
+          acc_mac(xi[v], a.y, o[1]);
+        }
+      }
+    }
+  } else {
+    const int64_t j0 = (c - tk.ncl) * tk.chj, j1 = j0 + tk.chj < N ? j0 + tk.chj : N;
+    for (int64_t j = j0; j < j1; ++j) {
+      double cr, ci = 0.0;
       if (CPLX) {
-        acc_mac(zr[v], -a.y, o[2]);
-        acc_mac(zr[v], -a.y, o[3]);
-        acc_mac(zi[v], a.x, o[2]);
-        acc_mac(zi[v], a.x, o[3]);
-        acc_mac(zi[v], a.y, o[0]);
-        acc_mac(zi[v], a.y, o[1]);
+        const double2 cz = reinterpret_cast<const double2 *>(tk.C)[i + j * tk.ldc];
+        cr = cz.x;
+        ci = cz.y;
+      } else {
+        cr = reinterpret_cast<const double *>(tk.C)[i + j * tk.ldc];
+      }
+      for (int v = 0; v < tk.nv; ++v) {
+        const double s = sign_of(tk.seed, v, N, j);
+        acc_add(xr[v], mul_rn(s, cr));
+        if (CPLX) acc_add(xi[v], mul_rn(s, ci));
       }
     }
   }
-  for (int64_t j = 0; j < n; ++j) {
-    double cr, ci = 0.0;
-    if (CPLX) {
-      const double2 c = reinterpret_cast<const double2 *>(C)[i + j * ldc];
-      cr = c.x;
-      ci = c.y;
-    } else {
-      cr = reinterpret_cast<const double *>(C)[i + j * ldc];
-    }
-    for (int v = 0; v < nv; ++v) {
-      const double s = sign_of(seed, v, n, j);
-      acc_add(yr[v], mul_rn(s, cr));
-      if (CPLX) acc_add(yi[v], mul_rn(s, ci));
-    }
-  }
+  put_rec(tk.p2 + (c * M + i) * kRec, xr, xi, tk.nv, u);
+}
+
+// Stage 4, thread i: z, y and u from the records in chunk order; est[i].
+__device__ void rows_sum(const ProbeTask &tk, int64_t i) {
+  const int64_t M = tk.va.R, N = tk.vb.R;
+  if (i >= M) return;
+  Dd zr[kMaxVec], zi[kMaxVec], yr[kMaxVec], yi[kMaxVec];
+  double u = 0.0, unused = 0.0;
+  for (int64_t c = 0; c < tk.ncl; ++c) add_rec(tk.p2 + (c * M + i) * kRec, zr, zi, tk.nv, u);
+  for (int64_t c = tk.ncl; c < tk.ncl + tk.ncj; ++c)
+    add_rec(tk.p2 + (c * M + i) * kRec, yr, yi, tk.nv, unused);
   double ss = 0.0;
   bool finite = true;
-  for (int v = 0; v < nv; ++v) {
+  for (int v = 0; v < tk.nv; ++v) {
     // hi parts agree to within the emulation error, so their difference is
     // exact (Sterbenz); the lo parts add the compensation.
     const double rr = add_rn(sub_rn(yr[v].hi, zr[v].hi), sub_rn(yr[v].lo, zr[v].lo));
@@ -167,15 +221,42 @@ __device__ void probe_rows(const View &va, const void *C, int64_t ldc, int64_t n
   else if (u == 0.0)
     e = ss == 0.0 ? 0.0 : __longlong_as_double(0x7ff0000000000000ll);
   else
-    e = sqrt(ss / nv) * sqrt((double)n) / u;
-  est[i] = e;
+    e = sqrt(ss / tk.nv) * sqrt((double)N) / u;
+  tk.est[i] = e;
 }
 
-template <bool CPLX>
-__global__ void __launch_bounds__(256) k_probe_rows(View va, const void *C, int64_t ldc, int64_t n,
-                                                    int nv, uint64_t seed, const double *w,
-                                                    const double *ub, double *est) {
-  probe_rows<CPLX>(va, C, ldc, n, nv, seed, w, ub, est, (int64_t)blockIdx.x * 256 + threadIdx.x);
+__device__ __forceinline__ void run_stage(const ProbeTask &tk, int stage, int64_t idx) {
+  switch (stage) {
+    case 0:
+      if (tk.cplx) bx_part<true>(tk, idx); else bx_part<false>(tk, idx);
+      break;
+    case 1: bx_sum(tk, idx); break;
+    case 2:
+      if (tk.cplx) rows_part<true>(tk, idx); else rows_part<false>(tk, idx);
+      break;
+    default: rows_sum(tk, idx); break;
+  }
+}
+
+// One problem: the task by value.
+__global__ void __launch_bounds__(256) k_probe_stage(ProbeTask tk, int stage) {
+  run_stage(tk, stage, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Batched: task t owns blocks tasks[t].blk[stage] .. tasks[t+1].blk[stage]-1.
+__global__ void __launch_bounds__(256) k_probe_stage_batched(const ProbeTask *tasks, int ntasks,
+                                                             int stage) {
+  int lo = 0, hi = ntasks - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].blk[stage] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const ProbeTask &tk = tasks[lo];
+  run_stage(tk, stage, (b - tk.blk[stage]) * 256 + threadIdx.x);
 }
 
 __device__ __forceinline__ int find_task3(const int64_t *start, int ntasks, int64_t b) {
@@ -190,28 +271,33 @@ __device__ __forceinline__ int find_task3(const int64_t *start, int ntasks, int6
   return lo;
 }
 
-// Batched forms: task t owns blocks start[t] .. start[t+1]-1 (k / 256 blocks
-// for the first kernel, m / 256 for the second).
-__global__ void __launch_bounds__(256) k_probe_bx_batched(const ProbeTask *tasks,
-                                                          const int64_t *start, int ntasks) {
-  const int t = find_task3(start, ntasks, blockIdx.x);
-  const ProbeTask tk = tasks[t];
-  const int64_t l = (blockIdx.x - start[t]) * 256 + threadIdx.x;
-  if (tk.cplx)
-    probe_bx<true>(tk.vb, tk.nv, tk.seed, tk.w, tk.ub, l);
-  else
-    probe_bx<false>(tk.vb, tk.nv, tk.seed, tk.w, tk.ub, l);
-}
-
-__global__ void __launch_bounds__(256) k_probe_rows_batched(const ProbeTask *tasks,
-                                                            const int64_t *start, int ntasks) {
-  const int t = find_task3(start, ntasks, blockIdx.x);
-  const ProbeTask tk = tasks[t];
-  const int64_t i = (blockIdx.x - start[t]) * 256 + threadIdx.x;
-  if (tk.cplx)
-    probe_rows<true>(tk.va, tk.C, tk.ldc, tk.vb.R, tk.nv, tk.seed, tk.w, tk.ub, tk.est, i);
-  else
-    probe_rows<false>(tk.va, tk.C, tk.ldc, tk.vb.R, tk.nv, tk.seed, tk.w, tk.ub, tk.est, i);
+// out[t] = max_i est_t[i] over the rows of task t (NaN if any row is NaN);
+// one workgroup per task.
+__global__ void __launch_bounds__(256) k_probe_max_batched(const ProbeTask *tasks, double *out) {
+  const ProbeTask &tk = tasks[blockIdx.x];
+  const int64_t M = tk.va.R;
+  double mx = 0.0;
+  bool nan = false;
+  for (int64_t i = threadIdx.x; i < M; i += 256) {
+    const double e = tk.est[i];
+    if (isnan(e))
+      nan = true;
+    else
+      mx = fmax(mx, e);
+  }
+  __shared__ double smax[256];
+  __shared__ int snan[256];
+  smax[threadIdx.x] = mx;
+  snan[threadIdx.x] = nan ? 1 : 0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      snan[threadIdx.x] |= snan[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = snan[0] ? qnan() : smax[0];
 }
 
 // C_p = alpha_p P_p + beta_p C_p for complex problems, the epilogue formula of
@@ -238,19 +324,76 @@ __global__ void __launch_bounds__(256) k_axpby_batched(const AxpbyTask *tasks, c
 
 }  // namespace
 
-int64_t probe_task_blocks_k(const ProbeTask &t) { return (t.vb.L + 255) / 256; }
-int64_t probe_task_blocks_m(const ProbeTask &t) { return (t.va.R + 255) / 256; }
+namespace {
+
+int64_t chunk_len(int64_t len) { return std::max<int64_t>(32, (len + 31) / 32); }
+int64_t chunks(int64_t len, int64_t ch) { return len <= 0 ? 0 : (len + ch - 1) / ch; }
+int64_t blocks(int64_t threads) { return (threads + 255) / 256; }
+
+}  // namespace
+
+size_t probe_workspace_bytes(int64_t m, int64_t n, int64_t k) {
+  const int64_t ncl = chunks(k, chunk_len(k)), ncj = chunks(n, chunk_len(n));
+  const size_t recs = (size_t)k + (size_t)ncj * k + (size_t)(ncl + ncj) * m;
+  return recs * kRec * sizeof(double) + 4 * 256;
+}
+
+ProbeTask probe_task(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc, int nv,
+                     uint64_t seed, void *ws, double *est) {
+  ProbeTask t{};
+  t.va = va;
+  t.vb = vb;
+  t.C = C;
+  t.ldc = ldc;
+  t.cplx = cplx ? 1 : 0;
+  t.nv = nv;
+  t.seed = seed;
+  t.est = est;
+  const int64_t M = va.R, K = va.L, N = vb.R;
+  t.chl = chunk_len(K);
+  t.chj = chunk_len(N);
+  t.ncl = chunks(K, t.chl);
+  t.ncj = chunks(N, t.chj);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  char *p = static_cast<char *>(ws);
+  t.w = reinterpret_cast<double *>(p);  // w (16 per l) and ub (1 per l) share one record each
+  t.ub = t.w + (size_t)K * kMaxVec * 4;
+  p += al((size_t)K * kRec * sizeof(double));
+  t.p1 = reinterpret_cast<double *>(p);
+  p += al((size_t)t.ncj * K * kRec * sizeof(double));
+  t.p2 = reinterpret_cast<double *>(p);
+  return t;
+}
+
 int64_t axpby_task_blocks(const AxpbyTask &t) { return (t.m * t.n + 255) / 256; }
 
-hipError_t launch_probe_batched(const ProbeTask *tasks, const int64_t *start_k, int64_t nblk_k,
-                                const int64_t *start_m, int64_t nblk_m, int ntasks, hipStream_t st) {
+int64_t probe_stage_blocks(const ProbeTask &t, int stage) {
+  const int64_t M = t.va.R, K = t.va.L;
+  switch (stage) {
+    case 0: return blocks(K * t.ncj);
+    case 1: return blocks(K);
+    case 2: return blocks(M * (t.ncl + t.ncj));
+    default: return blocks(M);
+  }
+}
+
+hipError_t launch_probe_batched(const ProbeTask *tasks, int ntasks, const int64_t *nblk,
+                                hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  if (nblk_k > 0)
-    hipLaunchKernelGGL(k_probe_bx_batched, dim3((unsigned)nblk_k), dim3(256), 0, st, tasks, start_k,
-                       ntasks);
-  if (nblk_m > 0)
-    hipLaunchKernelGGL(k_probe_rows_batched, dim3((unsigned)nblk_m), dim3(256), 0, st, tasks,
-                       start_m, ntasks);
+  for (int stage = 0; stage < 4; ++stage) {
+    if (nblk[stage] <= 0) continue;
+    hipLaunchKernelGGL(k_probe_stage_batched, dim3((unsigned)nblk[stage]), dim3(256), 0, st, tasks,
+                       ntasks, stage);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_probe_max_batched(const ProbeTask *tasks, int ntasks, double *out,
+                                    hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe_max_batched, dim3((unsigned)ntasks), dim3(256), 0, st, tasks, out);
   return hipGetLastError();
 }
 
@@ -261,31 +404,20 @@ hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, in
   return hipGetLastError();
 }
 
-size_t probe_workspace_bytes(int64_t k) { return (size_t)k * (kMaxVec * 4 + 1) * sizeof(double) + 256; }
 int probe_max_vectors() { return kMaxVec; }
 
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
-                        int64_t m, int64_t n, int64_t k, int nv, uint64_t seed, void *ws, double *est,
-                        hipStream_t st) {
-  if (m <= 0) return hipSuccess;
-  double *w = static_cast<double *>(ws);
-  double *ub = w + (size_t)k * kMaxVec * 4;
-  if (k > 0) {
-    const dim3 g((unsigned)((k + 255) / 256));
-    if (cplx)
-      hipLaunchKernelGGL(k_probe_bx<true>, g, dim3(256), 0, st, vb, nv, seed, w, ub);
-    else
-      hipLaunchKernelGGL(k_probe_bx<false>, g, dim3(256), 0, st, vb, nv, seed, w, ub);
-    hipError_t e = hipGetLastError();
+                        int nv, uint64_t seed, void *ws, double *est, hipStream_t st) {
+  if (va.R <= 0) return hipSuccess;
+  const ProbeTask t = probe_task(va, vb, cplx, C, ldc, nv, seed, ws, est);
+  for (int stage = 0; stage < 4; ++stage) {
+    const int64_t nb = probe_stage_blocks(t, stage);
+    if (nb <= 0) continue;
+    hipLaunchKernelGGL(k_probe_stage, dim3((unsigned)nb), dim3(256), 0, st, t, stage);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  (void)n;
-  const dim3 g((unsigned)((m + 255) / 256));
-  if (cplx)
-    hipLaunchKernelGGL(k_probe_rows<true>, g, dim3(256), 0, st, va, C, ldc, n, nv, seed, w, ub, est);
-  else
-    hipLaunchKernelGGL(k_probe_rows<false>, g, dim3(256), 0, st, va, C, ldc, n, nv, seed, w, ub, est);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace oz
