@@ -32,7 +32,7 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 matrix peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 GEMM_SOURCES = [os.path.join(ROOT, "paper_2603_29975_amd", "csrc", f)
-                for f in ("ozaki_gemm.hip", "ozaki_gemm_tile.hpp", "ozaki_gemm_w1.hip")]
+                for f in ("ozaki_gemm.hip", "ozaki_gemm_tile.hpp")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ozgemm_kkr2048_s7_traffic.txt")
 TUNE_CACHE = os.path.join(ROOT, "paper_2603_29975_amd", "tune_gfx950.json")
 

@@ -60,7 +60,7 @@ using tile::wait_vmcnt;
 
 template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED,
           bool EARLY>
-__global__ void __launch_bounds__(64 * WJ * WI) k_ozgemm(GemmArgs G) {
+__global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(GemmArgs G) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
   __shared__ __attribute__((aligned(16))) int8_t lds[C_::LDS];
 
@@ -210,8 +210,10 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   const int64_t ntiles =
       grouped ? a.ntiles
               : ((a.one.nprime + C_::BJ - 1) / C_::BJ) * ((a.one.m + C_::BI - 1) / C_::BI);
-  // one workgroup per CU is resident (LDS ring); persistent grid
-  const int64_t grid = std::min<int64_t>(ntiles, (int64_t)num_cu);
+  // persistent grid: 8 waves per CU, i.e. one workgroup of 8 waves or two of 4
+  // (whose barriers are independent, so one's MFMAs fill the other's waits)
+  const int64_t per_cu = C_::NW >= 8 ? 1 : 8 / C_::NW;
+  const int64_t grid = std::min<int64_t>(ntiles, per_cu * num_cu);
   if (grid <= 0) return hipSuccess;
   const dim3 g((unsigned)grid), b(C_::NT);
   if (grouped) {
@@ -244,13 +246,12 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //      three contraction blocks where it fits in 160 KiB (S <= 8), else two
 //   1: 2 along j' x 4 along i (64 j' x 128 i), same ring
 //   2: as 0 with a ring of two blocks (prefetch distance one)
-//   3: the one-wave-per-SIMD kernel of ozaki_gemm_w1.hip (same 128 j' x 64 i
-//      tile, two blocks per wave, fragments double-buffered in registers) for
-//      S <= 8 without contraction chunking; configuration 0 otherwise
-//   4: as 2 with every fragment read of a block issued before its MFMAs
+//   3: as 2 with every fragment read of a block issued before its MFMAs
+//   4: 4 waves (2 x 2), tile 64 j' x 64 i, ring of two, two workgroups per CU
+//   5: as 4 with the reads of 3
 // A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
 // down the rows i, 1: along the columns j').
-constexpr int kNumCfg = 5;
+constexpr int kNumCfg = 6;
 
 template <int CFG>
 struct Pick;
@@ -284,11 +285,9 @@ hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
   switch (cfg) {
     case 1: return launch_pick<S, 1>(a, num_cu, st);
     case 2: return launch_pick<S, 2>(a, num_cu, st);
-    case 3:
-      if (S <= gemm_w1_max_slices() && a.probs == nullptr && a.one.raw == nullptr && !a.chunked)
-        return launch_ozgemm_w1(S, a, num_cu, st);
-      return launch_pick<S, 0>(a, num_cu, st);
-    case 4: return launch_cfg<S, 4, 2, 1, 2, false, true>(a, num_cu, st);
+    case 3: return launch_cfg<S, 4, 2, 1, 2, false, true>(a, num_cu, st);
+    case 4: return launch_cfg<S, 2, 2, 1, 2, false, false>(a, num_cu, st);
+    case 5: return launch_cfg<S, 2, 2, 1, 2, false, true>(a, num_cu, st);
     default: return launch_pick<S, 0>(a, num_cu, st);
   }
 }
@@ -318,8 +317,9 @@ int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
   switch (cfg / 2) {
     case 1: BJ = 32 * Pick<1>::WJ; BI = 32 * Pick<1>::WI * Pick<1>::IB; break;
     case 2: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
-    case 3: BJ = gemm_w1_tile_j(); BI = gemm_w1_tile_i(); break;
-    case 4: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
+    case 3: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
+    case 4:
+    case 5: BJ = 64; BI = 64; break;
     default: BJ = 32 * Pick<0>::WJ; BI = 32 * Pick<0>::WI * Pick<0>::IB; break;
   }
   return ((nprime + BJ - 1) / BJ) * ((m + BI - 1) / BI);

@@ -101,13 +101,6 @@ int gemm_num_configs();
 // every configuration).
 size_t gemm_flush_bytes(int S, int cfg, int num_cu);
 hipError_t launch_ozgemm(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
-// One-wave-per-SIMD form of the fused GEMM (ozaki_gemm_w1.hip): single
-// problems without contraction chunking, S <= gemm_w1_max_slices(), tile
-// gemm_w1_tile_j() x gemm_w1_tile_i().
-int gemm_w1_max_slices();
-int64_t gemm_w1_tile_j();
-int64_t gemm_w1_tile_i();
-hipError_t launch_ozgemm_w1(int S, const GemmArgs &a, int num_cu, hipStream_t st);
 
 // Selector features and MLP (see ozaki_selector.hip).
 struct FeatTask {
