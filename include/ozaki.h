@@ -167,7 +167,8 @@ int ozaki_batched_cache_clear(void);
  * ozaki_zgemm and ozaki_debug_diagonals look their shape up there (default 0).
  * The environment variable OZAKI_GEMM_CONFIG=<id> forces one id for every call;
  * OZAKI_TUNE_CACHE=<file> loads a saved table before the first lookup.
- * The batched path always uses id 0.
+ * The batched path uses id 8 (four-wave 64 x 64 tiles, two workgroups per CU)
+ * unless OZAKI_BATCHED_CONFIG=<id> is set.
  *
  * ozaki_autotune: times the fused GEMM kernel of every id on an m x n x k
  *   product with `slices` slices on the library's stream: packed operands of

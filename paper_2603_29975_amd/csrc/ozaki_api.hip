@@ -456,6 +456,7 @@ struct BatchedPlan {
   std::vector<GroupDesc> groups;
   std::vector<ScaleOp> scales;
   std::vector<int> used;  // slices used per problem
+  int tune_id = 0;        // tile configuration of the grouped GEMM
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -516,7 +517,8 @@ int enqueue_plan(const BatchedPlan &pl, hipStream_t st, bool capturing) {
     a.flush_ws = reinterpret_cast<int64_t *>(base + pl.off_flush);
     a.kb_chunk = kb_chunk_for(gd.S);
     a.chunked = gd.chunked ? 1 : 0;
-    if ((rc = hip_rc(launch_ozgemm_grouped(gd.S, 0, a, g.dev[pl.dev].num_cu, st)))) return rc;
+    if ((rc = hip_rc(launch_ozgemm_grouped(gd.S, pl.tune_id, a, g.dev[pl.dev].num_cu, st))))
+      return rc;
   }
   phase_end(mk, st);
   if (timed && g_tm.on) ++g_tm.calls;
@@ -527,6 +529,19 @@ int enqueue_plan(const BatchedPlan &pl, hipStream_t st, bool capturing) {
 }
 
 // Builds (or finds) the plan of a validated batched call.
+// Tile configuration of the grouped GEMM of batched calls: OZAKI_BATCHED_CONFIG
+// (a tuning id) or the default 8, the four-wave 64 x 64 tiles (two workgroups
+// per CU), which waste less padding on the small problems of a batch.
+int batched_tune_id() {
+  static int id = -2;
+  if (id == -2) {
+    const char *e = getenv("OZAKI_BATCHED_CONFIG");
+    id = (e != nullptr && *e) ? atoi(e) : -1;
+    if (id >= gemm_num_configs()) id = -1;
+  }
+  return id >= 0 ? id : 8;
+}
+
 // Lays out one batched plan: problem descriptors, scan and split task tables,
 // tile tables (one group per slice count, longest contraction first) and the
 // workspace of every emulated problem. alloc(total) provides the device memory
@@ -540,6 +555,7 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
                const int *slices, int num_cu, BatchedPlan *pl, Alloc alloc,
                std::vector<uint8_t> &host) {
   pl->used.assign((size_t)batch, 0);
+  pl->tune_id = batched_tune_id();
   std::vector<GemmProblem> probs;
   std::vector<ScanTask> scans;
   std::vector<SplitTask> splits;
@@ -579,7 +595,7 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
   // tile tables, one group per distinct slice count, longest contraction first
   std::map<int, std::vector<std::pair<int, int>>> tiles;  // S -> (problem, local tile)
   for (size_t i = 0; i < np; ++i) {
-    const int64_t nt = gemm_tiles(prob_S[i], 0, plans[i].m, plans[i].nprime);
+    const int64_t nt = gemm_tiles(prob_S[i], pl->tune_id, plans[i].m, plans[i].nprime);
     for (int64_t t = 0; t < nt; ++t) tiles[prob_S[i]].push_back({(int)i, (int)t});
   }
   for (auto &kv : tiles)
