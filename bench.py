@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2603_29975_amd",
                                                          "selector_weights.npz"),
                     help="trained selector weights (selector512 workload)")
+    ap.add_argument("--kappa", type=float, default=8.0,
+                    help="selector512: probe safety factor (estimate * kappa must meet the target)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (timing and accuracy check)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -387,7 +389,7 @@ def run_selector(args):
     count on the 512-problem batch, at a componentwise target of 1e-11."""
     from paper_2603_29975_amd import selector
     theta, margin, target = selector.load(args.selector)
-    res = selector.evaluate_gain(theta, margin, target, steps=args.steps, log=log)
+    res = selector.evaluate_gain(theta, margin, target, kappa=args.kappa, steps=args.steps, log=log)
     flops = None
     from workloads import batched_problems
     import numpy as np
@@ -399,7 +401,8 @@ def run_selector(args):
         "ms_per_step": round(res["ms_learned"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int8", "data": "synthetic",
         "config": {"workload": "batched_zgemm_512_learned_slices", "target_err_comp": target,
-                   "selector": os.path.basename(args.selector), "margin": margin, "seed": 1003},
+                   "selector": os.path.basename(args.selector), "margin": margin,
+                   "kappa": args.kappa, "seed": 1003},
         "roofline": None, "cpu_baseline": None, "selector": res,
     }
     print(json.dumps(out), flush=True)

@@ -906,7 +906,6 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     return o;
   };
   std::vector<size_t> o_codeA(ne), o_codeB(ne), o_P(ne), o_w(ne), o_est(ne);
-  int64_t sum_m = 0;
   for (int64_t e = 0; e < ne; ++e) {
     const int64_t b = E[e];
     o_codeA[e] = take(sizeof(int) * m[b]);
@@ -914,7 +913,6 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     o_P[e] = take(sizeof(ozaki_z) * m[b] * n[b]);
     o_w[e] = take(probe_workspace_bytes(m[b], n[b], k[b]));
     o_est[e] = take(sizeof(double) * m[b]);
-    sum_m += m[b];
   }
   const size_t o_hist = take(sizeof(int) * 64 * ne), o_dims = take(sizeof(int64_t) * 3 * ne),
                o_feat = take(sizeof(float) * 64 * ne), o_y = take(sizeof(float) * ne),

@@ -248,7 +248,7 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //   2: as 0 with a ring of two blocks (prefetch distance one)
 //   3: as 2 with every fragment read of a block issued before its MFMAs
 //   4: 4 waves (2 x 2), tile 64 j' x 64 i, ring of two, two workgroups per CU
-//   5: as 4 with the reads of 3
+//   5: as 4 with the reads of 3 (4 and 5 fall back to 2 for S >= 11)
 // A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
 // down the rows i, 1: along the columns j').
 constexpr int kNumCfg = 6;
@@ -286,8 +286,16 @@ hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
     case 1: return launch_pick<S, 1>(a, num_cu, st);
     case 2: return launch_pick<S, 2>(a, num_cu, st);
     case 3: return launch_cfg<S, 4, 2, 1, 2, false, true>(a, num_cu, st);
-    case 4: return launch_cfg<S, 2, 2, 1, 2, false, false>(a, num_cu, st);
-    case 5: return launch_cfg<S, 2, 2, 1, 2, false, true>(a, num_cu, st);
+    case 4:
+    case 5:
+      // two four-wave workgroups per CU need <= 256 registers per wave, which
+      // the accumulators of S >= 11 exceed: configuration 2 there
+      if constexpr (S <= 10) {
+        if (cfg == 4) return launch_cfg<S, 2, 2, 1, 2, false, false>(a, num_cu, st);
+        return launch_cfg<S, 2, 2, 1, 2, false, true>(a, num_cu, st);
+      } else {
+        return launch_pick<S, 2>(a, num_cu, st);
+      }
     default: return launch_pick<S, 0>(a, num_cu, st);
   }
 }
@@ -312,14 +320,21 @@ size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
 }
 
 int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
-  (void)S;
   int64_t BJ, BI;
   switch (cfg / 2) {
     case 1: BJ = 32 * Pick<1>::WJ; BI = 32 * Pick<1>::WI * Pick<1>::IB; break;
     case 2: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
     case 3: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
     case 4:
-    case 5: BJ = 64; BI = 64; break;
+    case 5:
+      if (S <= 10) {
+        BJ = 64;
+        BI = 64;
+      } else {  // launched as configuration 2
+        BJ = 32 * Pick<2>::WJ;
+        BI = 32 * Pick<2>::WI * Pick<2>::IB;
+      }
+      break;
     default: BJ = 32 * Pick<0>::WJ; BI = 32 * Pick<0>::WI * Pick<0>::IB; break;
   }
   return ((nprime + BJ - 1) / BJ) * ((m + BI - 1) / BI);

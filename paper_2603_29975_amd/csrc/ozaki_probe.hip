@@ -84,8 +84,10 @@ __device__ __forceinline__ double2 ld(const View &v, int64_t r, int64_t l) {
 // compensated sums (re.hi, re.lo, im.hi, im.lo) and one plain sum.
 constexpr int kRec = kMaxVec * 4 + 1;
 
-__device__ __forceinline__ void put_rec(double *o, const Dd *re, const Dd *im, int nv, double u) {
-  for (int v = 0; v < nv; ++v) {
+template <int NV>
+__device__ __forceinline__ void put_rec(double *o, const Dd *re, const Dd *im, double u) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     o[v * 4 + 0] = re[v].hi;
     o[v * 4 + 1] = re[v].lo;
     o[v * 4 + 2] = im[v].hi;
@@ -94,8 +96,10 @@ __device__ __forceinline__ void put_rec(double *o, const Dd *re, const Dd *im, i
   o[kMaxVec * 4] = u;
 }
 
-__device__ __forceinline__ void add_rec(const double *o, Dd *re, Dd *im, int nv, double &u) {
-  for (int v = 0; v < nv; ++v) {
+template <int NV>
+__device__ __forceinline__ void add_rec(const double *o, Dd *re, Dd *im, double &u) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     acc_add(re[v], o[v * 4 + 0]);
     re[v].lo = add_rn(re[v].lo, o[v * 4 + 1]);
     acc_add(im[v], o[v * 4 + 2]);
@@ -107,7 +111,7 @@ __device__ __forceinline__ void add_rec(const double *o, Dd *re, Dd *im, int nv,
 // Stage 1, thread (l, chunk c of columns j): partial w_v[l] = sum_j op(B)(l, j)
 // x_v[j] and ub[l] = sum_j |op(B)(l, j)|. vb views op(B) with rows = columns
 // j and contraction = l, so op(B)(l, j) = vb(j, l).
-template <bool CPLX>
+template <bool CPLX, int NV>
 __device__ void bx_part(const ProbeTask &tk, int64_t idx) {
   const int64_t K = tk.vb.L, N = tk.vb.R;
   if (idx >= K * tk.ncj) return;
@@ -118,24 +122,27 @@ __device__ void bx_part(const ProbeTask &tk, int64_t idx) {
   for (int64_t j = j0; j < j1; ++j) {
     const double2 b = ld<CPLX>(tk.vb, j, l);
     u = add_rn(u, CPLX ? hypot(b.x, b.y) : fabs(b.x));
-    for (int v = 0; v < tk.nv; ++v) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
       const double s = sign_of(tk.seed, v, N, j);
       acc_add(re[v], mul_rn(s, b.x));
       if (CPLX) acc_add(im[v], mul_rn(s, b.y));
     }
   }
-  put_rec(tk.p1 + (c * K + l) * kRec, re, im, tk.nv, u);
+  put_rec<NV>(tk.p1 + (c * K + l) * kRec, re, im, u);
 }
 
 // Stage 2, thread l: w[l] (per v: re.hi, re.lo, im.hi, im.lo) and ub[l] from
 // the chunk records in order.
+template <int NV>
 __device__ void bx_sum(const ProbeTask &tk, int64_t l) {
   const int64_t K = tk.vb.L;
   if (l >= K) return;
   Dd re[kMaxVec], im[kMaxVec];
   double u = 0.0;
-  for (int64_t c = 0; c < tk.ncj; ++c) add_rec(tk.p1 + (c * K + l) * kRec, re, im, tk.nv, u);
-  for (int v = 0; v < tk.nv; ++v) {
+  for (int64_t c = 0; c < tk.ncj; ++c) add_rec<NV>(tk.p1 + (c * K + l) * kRec, re, im, u);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     double *o = tk.w + (l * kMaxVec + v) * 4;
     o[0] = re[v].hi;
     o[1] = re[v].lo;
@@ -148,7 +155,7 @@ __device__ void bx_sum(const ProbeTask &tk, int64_t l) {
 // Stage 3, thread (i, chunk c): for c < ncl the partial z_v = sum_l op(A)(i, l)
 // w_v[l] (w as hi + lo) and u = sum_l |op(A)(i, l)| ub[l] over a chunk of l;
 // for c >= ncl the partial y_v = sum_j C(i, j) x_v[j] over a chunk of j.
-template <bool CPLX>
+template <bool CPLX, int NV>
 __device__ void rows_part(const ProbeTask &tk, int64_t idx) {
   const int64_t M = tk.va.R, K = tk.va.L, N = tk.vb.R;
   if (idx >= M * (tk.ncl + tk.ncj)) return;
@@ -160,7 +167,8 @@ __device__ void rows_part(const ProbeTask &tk, int64_t idx) {
     for (int64_t l = l0; l < l1; ++l) {
       const double2 a = ld<CPLX>(tk.va, i, l);
       u = add_rn(u, mul_rn(CPLX ? hypot(a.x, a.y) : fabs(a.x), tk.ub[l]));
-      for (int v = 0; v < tk.nv; ++v) {
+  #pragma unroll
+    for (int v = 0; v < NV; ++v) {
         const double *o = tk.w + (l * kMaxVec + v) * 4;
         // (ar + i ai)(wr + i wi) with w = hi + lo in both parts
         acc_mac(xr[v], a.x, o[0]);
@@ -186,28 +194,31 @@ __device__ void rows_part(const ProbeTask &tk, int64_t idx) {
       } else {
         cr = reinterpret_cast<const double *>(tk.C)[i + j * tk.ldc];
       }
-      for (int v = 0; v < tk.nv; ++v) {
+  #pragma unroll
+    for (int v = 0; v < NV; ++v) {
         const double s = sign_of(tk.seed, v, N, j);
         acc_add(xr[v], mul_rn(s, cr));
         if (CPLX) acc_add(xi[v], mul_rn(s, ci));
       }
     }
   }
-  put_rec(tk.p2 + (c * M + i) * kRec, xr, xi, tk.nv, u);
+  put_rec<NV>(tk.p2 + (c * M + i) * kRec, xr, xi, u);
 }
 
 // Stage 4, thread i: z, y and u from the records in chunk order; est[i].
+template <int NV>
 __device__ void rows_sum(const ProbeTask &tk, int64_t i) {
   const int64_t M = tk.va.R, N = tk.vb.R;
   if (i >= M) return;
   Dd zr[kMaxVec], zi[kMaxVec], yr[kMaxVec], yi[kMaxVec];
   double u = 0.0, unused = 0.0;
-  for (int64_t c = 0; c < tk.ncl; ++c) add_rec(tk.p2 + (c * M + i) * kRec, zr, zi, tk.nv, u);
+  for (int64_t c = 0; c < tk.ncl; ++c) add_rec<NV>(tk.p2 + (c * M + i) * kRec, zr, zi, u);
   for (int64_t c = tk.ncl; c < tk.ncl + tk.ncj; ++c)
-    add_rec(tk.p2 + (c * M + i) * kRec, yr, yi, tk.nv, unused);
+    add_rec<NV>(tk.p2 + (c * M + i) * kRec, yr, yi, unused);
   double ss = 0.0;
   bool finite = true;
-  for (int v = 0; v < tk.nv; ++v) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
     // hi parts agree to within the emulation error, so their difference is
     // exact (Sterbenz); the lo parts add the compensation.
     const double rr = add_rn(sub_rn(yr[v].hi, zr[v].hi), sub_rn(yr[v].lo, zr[v].lo));
@@ -221,20 +232,32 @@ __device__ void rows_sum(const ProbeTask &tk, int64_t i) {
   else if (u == 0.0)
     e = ss == 0.0 ? 0.0 : __longlong_as_double(0x7ff0000000000000ll);
   else
-    e = sqrt(ss / tk.nv) * sqrt((double)N) / u;
+    e = sqrt(ss / NV) * sqrt((double)N) / u;
   tk.est[i] = e;
 }
 
-__device__ __forceinline__ void run_stage(const ProbeTask &tk, int stage, int64_t idx) {
+template <int NV>
+__device__ __forceinline__ void run_stage_nv(const ProbeTask &tk, int stage, int64_t idx) {
   switch (stage) {
     case 0:
-      if (tk.cplx) bx_part<true>(tk, idx); else bx_part<false>(tk, idx);
+      if (tk.cplx) bx_part<true, NV>(tk, idx); else bx_part<false, NV>(tk, idx);
       break;
-    case 1: bx_sum(tk, idx); break;
+    case 1: bx_sum<NV>(tk, idx); break;
     case 2:
-      if (tk.cplx) rows_part<true>(tk, idx); else rows_part<false>(tk, idx);
+      if (tk.cplx) rows_part<true, NV>(tk, idx); else rows_part<false, NV>(tk, idx);
       break;
-    default: rows_sum(tk, idx); break;
+    default: rows_sum<NV>(tk, idx); break;
+  }
+}
+
+// The vector count is a template parameter so that every per-vector sum lives
+// in registers (a runtime count would put them in scratch memory).
+__device__ __forceinline__ void run_stage(const ProbeTask &tk, int stage, int64_t idx) {
+  switch (tk.nv) {
+    case 1: run_stage_nv<1>(tk, stage, idx); break;
+    case 2: run_stage_nv<2>(tk, stage, idx); break;
+    case 3: run_stage_nv<3>(tk, stage, idx); break;
+    default: run_stage_nv<4>(tk, stage, idx); break;
   }
 }
 
@@ -349,7 +372,7 @@ ProbeTask probe_task(const View &va, const View &vb, bool cplx, const void *C, i
   t.nv = nv;
   t.seed = seed;
   t.est = est;
-  const int64_t M = va.R, K = va.L, N = vb.R;
+  const int64_t K = va.L, N = vb.R;
   t.chl = chunk_len(K);
   t.chj = chunk_len(N);
   t.ncl = chunks(K, t.chl);

@@ -382,6 +382,8 @@ def evaluate_gain(theta, margin, target, kappa=8.0, pairs=None, steps=5, log=Non
         "max_err_learned": float(err_auto.max()),
         "problems_raised_by_probe_or_over_label": int(np.sum(s_auto > np.minimum(labels, S_HI))),
         "problems_below_label": int(np.sum(s_auto < np.minimum(labels, S_HI))),
+        "problems_over_target": int(np.sum(err_auto > target)),
+        "kappa": kappa,
     }
     res["int8_work_ratio_learned_over_fixed"] = res["int8_ops_learned"] / res["int8_ops_fixed"]
     if log:
