@@ -118,9 +118,45 @@ __device__ __forceinline__ uint64_t top_bits(const Sig &x) {
   return (sh > -64) ? (x.m >> (-sh)) : 0ull;
 }
 
-template <bool CPLX, bool SIDEB, int SC>
+// View rows and contraction entries (elements) covered by one split block.
+template <bool CPLX, bool SIDEB>
+struct SplitTile {
+  static constexpr int TR = (CPLX && SIDEB) ? 32 : 64;  // view rows
+  static constexpr int TL = CPLX ? 32 : 64;              // contraction elements
+  static constexpr int EW = CPLX ? 2 : 1;                // doubles per element
+  static constexpr int PITCH = (TL + 1) * EW;            // doubles per LDS row (padded)
+};
+constexpr int kSplitTileDoubles = 64 * 33 * 2;  // the largest tile (complex, 64 rows)
+
+// When the contraction is the unit-stride direction (sl == 1) a thread's 16
+// packed entries lie along one row in memory, and the lanes of a wave would
+// read 64 different rows. The block then first copies its tile into LDS with
+// consecutive threads on consecutive elements of a row (coalesced), and the
+// threads take their values from there. Rows or elements outside the view
+// are stored as zeros.
+template <bool CPLX, bool SIDEB>
+__device__ __forceinline__ void load_split_tile(const View &v, int64_t bx, int64_t by, double *tile) {
+  using T = SplitTile<CPLX, SIDEB>;
+  const int64_t r0 = bx * T::TR, l0 = by * T::TL;
+  for (int c = threadIdx.x; c < T::TR * T::TL; c += 256) {
+    const int rr = c / T::TL, ll = c % T::TL;
+    const int64_t r = r0 + rr, l = l0 + ll;
+    const bool in = r < v.R && l < v.L;
+    if (CPLX) {
+      double2 z = make_double2(0.0, 0.0);
+      if (in) z = reinterpret_cast<const double2 *>(v.base)[r * v.sr + l];
+      *reinterpret_cast<double2 *>(tile + rr * T::PITCH + ll * 2) = z;
+    } else {
+      tile[rr * T::PITCH + ll] = in ? reinterpret_cast<const double *>(v.base)[r * v.sr + l] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+template <bool CPLX, bool SIDEB, int SC, bool TRP>
 __device__ __forceinline__ void split_block(const View &v, const int *code, int S, int8_t *out,
-                                            int64_t nrb, int64_t nkb, int64_t bx, int64_t by) {
+                                            int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
+                                            const double *tile) {
   const int tid = threadIdx.x;
   const int64_t rp = bx * 64 + (tid & 63);
   const int64_t kp0 = (by * 4 + (tid >> 6)) * 16;
@@ -139,7 +175,14 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
       const int64_t l = (kp0 >> 1) + x;
       double re = 0.0, im = 0.0;
       if (live && l < v.L) {
-        const double2 z = X[r * v.sr + l * v.sl];
+        double2 z;
+        if constexpr (TRP) {
+          using T = SplitTile<CPLX, SIDEB>;
+          z = *reinterpret_cast<const double2 *>(tile + (r - bx * T::TR) * T::PITCH +
+                                                 (l - by * T::TL) * 2);
+        } else {
+          z = X[r * v.sr + l * v.sl];
+        }
         re = z.x;
         im = v.conj ? -z.y : z.y;
       }
@@ -163,7 +206,14 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
     for (int x = 0; x < 16; ++x) {
       const int64_t l = kp0 + x;
       double val = 0.0;
-      if (live && l < v.L) val = X[r * v.sr + l * v.sl];
+      if (live && l < v.L) {
+        if constexpr (TRP) {
+          using T = SplitTile<CPLX, SIDEB>;
+          val = tile[(r - bx * T::TR) * T::PITCH + (l - by * T::TL)];
+        } else {
+          val = X[r * v.sr + l * v.sl];
+        }
+      }
       sg[x] = decompose(val, e);
     }
   }
@@ -213,23 +263,48 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
   }
 }
 
-template <bool CPLX, bool SIDEB>
-__device__ __forceinline__ void split_dispatch(const View &v, const int *code, int S, int8_t *out,
-                                               int64_t nrb, int64_t nkb, int64_t bx, int64_t by) {
+template <bool CPLX, bool SIDEB, bool TRP>
+__device__ __forceinline__ void split_s(const View &v, const int *code, int S, int8_t *out,
+                                        int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
+                                        const double *tile) {
   switch (S) {
 #define OZ_SPLIT(N) \
-  case N: split_block<CPLX, SIDEB, N>(v, code, S, out, nrb, nkb, bx, by); break;
+  case N: split_block<CPLX, SIDEB, N, TRP>(v, code, S, out, nrb, nkb, bx, by, tile); break;
     OZ_SPLIT(1) OZ_SPLIT(2) OZ_SPLIT(3) OZ_SPLIT(4) OZ_SPLIT(5) OZ_SPLIT(6) OZ_SPLIT(7)
     OZ_SPLIT(8) OZ_SPLIT(9)
 #undef OZ_SPLIT
-    default: split_block<CPLX, SIDEB, 0>(v, code, S, out, nrb, nkb, bx, by); break;
+    default: split_block<CPLX, SIDEB, 0, TRP>(v, code, S, out, nrb, nkb, bx, by, tile); break;
   }
 }
 
+// The LDS-staged form is taken when the contraction is unit-stride and the
+// rows are not (the choice is uniform over the block) and the caller provides
+// the LDS tile.
+__host__ __device__ __forceinline__ bool split_staged(const View &v) {
+  return v.sl == 1 && v.sr != 1;
+}
+
 template <bool CPLX, bool SIDEB>
+__device__ __forceinline__ void split_dispatch(const View &v, const int *code, int S, int8_t *out,
+                                               int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
+                                               double *tile) {
+  if (tile != nullptr && split_staged(v)) {
+    load_split_tile<CPLX, SIDEB>(v, bx, by, tile);
+    split_s<CPLX, SIDEB, true>(v, code, S, out, nrb, nkb, bx, by, tile);
+  } else {
+    split_s<CPLX, SIDEB, false>(v, code, S, out, nrb, nkb, bx, by, nullptr);
+  }
+}
+
+template <bool CPLX, bool SIDEB, bool STAGED>
 __global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
                                                int64_t nrb, int64_t nkb) {
-  split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y);
+  if constexpr (STAGED) {
+    __shared__ __attribute__((aligned(16))) double tile[kSplitTileDoubles];
+    split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, tile);
+  } else {
+    split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------- batched
@@ -277,13 +352,14 @@ __global__ void __launch_bounds__(256) k_split_batched(const SplitTask *tasks, c
   const int64_t local = b - start[t];
   const int64_t nbx = tk.nrb / 2;
   const int64_t bx = local % nbx, by = local / nbx;
+  __shared__ __attribute__((aligned(16))) double tile[kSplitTileDoubles];
   if (tk.cplx) {
     if (tk.side_b)
-      split_dispatch<true, true>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+      split_dispatch<true, true>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by, tile);
     else
-      split_dispatch<true, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+      split_dispatch<true, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by, tile);
   } else {
-    split_dispatch<false, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by);
+    split_dispatch<false, false>(tk.v, tk.code, tk.S, tk.out, tk.nrb, tk.nkb, bx, by, tile);
   }
 }
 
@@ -391,14 +467,17 @@ hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, 
   // nrb * 32 is a multiple of 64 (rows padded to 128) and nkb * 32 a multiple
   // of 64 (contraction padded to 64): the grid covers the buffer exactly.
   dim3 g((unsigned)(nrb * 32 / 64), (unsigned)(nkb * 32 / 64));
-  if (cplx) {
-    if (side_b)
-      hipLaunchKernelGGL((k_split<true, true>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
-    else
-      hipLaunchKernelGGL((k_split<true, false>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
+#define OZ_SPLIT_LAUNCH(C, B, T) \
+  hipLaunchKernelGGL((k_split<C, B, T>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb)
+  const bool staged = split_staged(v);
+  if (cplx && side_b) {
+    if (staged) OZ_SPLIT_LAUNCH(true, true, true); else OZ_SPLIT_LAUNCH(true, true, false);
+  } else if (cplx) {
+    if (staged) OZ_SPLIT_LAUNCH(true, false, true); else OZ_SPLIT_LAUNCH(true, false, false);
   } else {
-    hipLaunchKernelGGL((k_split<false, false>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb);
+    if (staged) OZ_SPLIT_LAUNCH(false, false, true); else OZ_SPLIT_LAUNCH(false, false, false);
   }
+#undef OZ_SPLIT_LAUNCH
   return hipGetLastError();
 }
 
