@@ -1,6 +1,6 @@
 /*
- * ozaki.h - C ABI of the MI355X (gfx950) Ozaki-I FP64 / complex-FP64 GEMM
- * emulator (libozaki.so).
+ * ozaki.h - C ABI of the MI355X (gfx950) Ozaki-I and Ozaki-II FP64 /
+ * complex-FP64 GEMM emulator (libozaki.so).
  *
  * The method is the Ozaki-I scheme as the paper describes it (Section 2.2,
  * GEMM Emulation on Integer Matrix Multiplication Unit): exponent alignment,
@@ -88,6 +88,50 @@ int ozaki_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
 int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                 ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb,
                 ozaki_z beta, ozaki_z *C, int64_t ldc, int slices);
+
+/*
+ * Ozaki-II emulation (Section 2.2: the inputs become integer matrices, their
+ * products are taken modulo several pairwise-coprime moduli on the INT8
+ * matrix cores and the Chinese remainder theorem rebuilds the result;
+ * Section 3 uses 10..18 moduli). C <- alpha op(A) op(B) + beta C with
+ * `moduli` moduli. Rules, on top of the exponents, alpha/beta and non-finite
+ * rules above:
+ *   moduli     the `moduli` largest pairwise-coprime integers <= 256, taken
+ *              greedily from 256 downwards (256, 255, 253, 251, 247, 241,
+ *              239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191, 181,
+ *              179, 173); M is their product.
+ *   integers   K' = k (real) or 2k (complex); beta = min(63, floor((floor(log2
+ *              M) - 1 - ceil(log2 K')) / 2)); A'_il = trunc(a_il 2^(beta -
+ *              e_i)), B'_lj = trunc(b_lj 2^(beta - f_j)) (Re and Im apart).
+ *   products   A' mod m_q, B' mod m_q as balanced residues in [-floor(m_q/2),
+ *              ceil(m_q/2) - 1]; one exact INT8 x INT8 -> INT32 product per
+ *              modulus (complex data: one real product of A' rows (Re, Im)
+ *              and B' rows (Re, -Im), (Im, Re) along the interleaved
+ *              contraction).
+ *   rebuild    c = the integer in [-M/2, M/2) congruent to every product mod
+ *              m_q; it equals A'B' exactly. P_ij = RN(c) 2^(e_i + f_j - 2 beta)
+ *              (one rounding), then alpha/beta.
+ * Argument numbers as ozaki_dgemm, with moduli 14 (OZAKI2_MODULI_MIN ..
+ * OZAKI2_MODULI_MAX, and -14 also when beta < 1: too few moduli for K').
+ * K' above OZAKI2_K_MAX (exact INT32 sums) returns -5. The workspace holds
+ * the residue planes and the INT32 products: see ozaki2_workspace_bytes.
+ */
+#define OZAKI2_MODULI_MIN 2
+#define OZAKI2_MODULI_MAX 20
+#define OZAKI2_K_MAX 131072
+int ozaki2_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                 double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double beta, double *C, int64_t ldc, int moduli);
+int ozaki2_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                 ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb,
+                 ozaki_z beta, ozaki_z *C, int64_t ldc, int moduli);
+/* Host-side queries (no device work): the first `moduli` moduli into out[]
+ * (host array); beta for `moduli` moduli and contraction length K' (0 when
+ * beta < 1, negative for arguments out of range); workspace bytes of one
+ * call (0 for invalid arguments or sizes the path rejects). */
+int ozaki2_moduli(int moduli, int32_t *out);
+int ozaki2_beta_bits(int moduli, int64_t kprime);
+size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int moduli);
 
 /*
  * Native FP64 GEMM on the FP64 matrix cores (the comparator the paper uses as
@@ -278,20 +322,25 @@ size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int sli
  *   OZAKI_PHASE_SCAN  exponent scan of op(A) rows and op(B) columns
  *   OZAKI_PHASE_SPLIT slicing of both operands into packed INT8 slices
  *   OZAKI_PHASE_GEMM  fused slice-pair INT8 GEMM + FP64 recombination
+ *                     (Ozaki-II: the INT8 residue products)
+ *   OZAKI_PHASE_RECON Ozaki-II only: CRT rebuild, scaling and alpha/beta
+ * (Ozaki-II records its residue step as OZAKI_PHASE_SPLIT.)
  * ozaki_timing_read waits for the recorded events, writes the summed
  * milliseconds per phase into ms[0..OZAKI_PHASES-1] (host array) and the
  * number of timed calls into *calls (may be NULL), then clears the record.
  * Recording adds one event pair per phase and call; leave it off otherwise.
  */
-#define OZAKI_PHASES 3
+#define OZAKI_PHASES 4
 #define OZAKI_PHASE_SCAN 0
 #define OZAKI_PHASE_SPLIT 1
 #define OZAKI_PHASE_GEMM 2
+#define OZAKI_PHASE_RECON 3
 int ozaki_timing_enable(int on);
 int ozaki_timing_read(double *ms, int64_t *calls);
 
-/* Release the library's own device buffers: the workspace and the scratch of
- * the automatic slice mode (safe to call more than once). */
+/* Release the library's own device buffers: the workspace, the scratch of
+ * the automatic slice mode and the Ozaki-II library-GEMM handles (safe to
+ * call more than once). */
 int ozaki_finalize(void);
 
 /* Static text for a status code. */

@@ -29,11 +29,15 @@ __all__ = [
     "ozaki_mlp_forward", "ozaki_mlp_backward", "ozaki_mlp_adam", "MLP_PARAMS",
     "ozaki_load_selector", "ozaki_autotune", "ozaki_tune_set", "ozaki_tune_get",
     "ozaki_tune_configs", "ozaki_tune_save", "ozaki_tune_load", "ozaki_tune_clear",
+    "ozaki2_dgemm", "ozaki2_zgemm", "ozaki2_moduli", "ozaki2_beta_bits", "ozaki2_workspace_bytes",
+    "MODULI_MIN", "MODULI_MAX", "K2_MAX",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libozaki.so")
 S_MAX = 12
+MODULI_MIN, MODULI_MAX = 2, 20   # Ozaki-II moduli counts
+K2_MAX = 131072                  # Ozaki-II contraction length K' (k, or 2k complex)
 
 
 class OzakiUnavailable(ImportError):
@@ -58,6 +62,13 @@ _SIG = {
                                _i64, _c.c_double, _vp, _i64, _c.c_int]),
     "ozaki_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
                                _i64, ozaki_z, _vp, _i64, _c.c_int]),
+    "ozaki2_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp, _i64, _vp,
+                                _i64, _c.c_double, _vp, _i64, _c.c_int]),
+    "ozaki2_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
+                                _i64, ozaki_z, _vp, _i64, _c.c_int]),
+    "ozaki2_moduli": (_c.c_int, [_c.c_int, _vp]),
+    "ozaki2_beta_bits": (_c.c_int, [_c.c_int, _i64]),
+    "ozaki2_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
     "ozaki_native_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp,
                                       _i64, _vp, _i64, _c.c_double, _vp, _i64]),
     "ozaki_native_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64,
@@ -153,6 +164,33 @@ def ozaki_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, sl
     _bind_stream()
     return library().ozaki_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
                                  _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(slices))
+
+
+def ozaki2_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, moduli) -> int:
+    _bind_stream()
+    return library().ozaki2_dgemm(_ch(transa), _ch(transb), m, n, k, float(alpha), _ptr(A), lda,
+                                  _ptr(B), ldb, float(beta), _ptr(C), ldc, int(moduli))
+
+
+def ozaki2_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, moduli) -> int:
+    _bind_stream()
+    return library().ozaki2_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
+                                  _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(moduli))
+
+
+def ozaki2_moduli(moduli):
+    """(status, list of the first `moduli` moduli); host-side query."""
+    out = (_c.c_int32 * max(int(moduli), 1))()
+    rc = library().ozaki2_moduli(int(moduli), _c.cast(out, _c.c_void_p))
+    return rc, [out[i] for i in range(int(moduli))] if rc == 0 else []
+
+
+def ozaki2_beta_bits(moduli, kprime) -> int:
+    return library().ozaki2_beta_bits(int(moduli), int(kprime))
+
+
+def ozaki2_workspace_bytes(kind, m, n, k, moduli) -> int:
+    return library().ozaki2_workspace_bytes(_ch(kind), m, n, k, int(moduli))
 
 
 def ozaki_native_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc) -> int:
@@ -316,7 +354,7 @@ def ozaki_workspace_bytes(kind, m, n, k, slices) -> int:
     return library().ozaki_workspace_bytes(_ch(kind), m, n, k, int(slices))
 
 
-PHASES = ("scan", "split", "gemm")
+PHASES = ("scan", "split", "gemm", "recon")
 
 
 def ozaki_timing_enable(on: bool) -> int:
@@ -360,9 +398,11 @@ def ozaki_debug_diagonals(kind, transa, transb, m, n, k, A, lda, B, ldb, slices,
                                            lda, _ptr(B), ldb, int(slices), _ptr(S))
 
 
-def matmul(A, B, slices: int = 7, alpha=1.0, beta=0.0, C=None, native: bool = False):
+def matmul(A, B, slices: int = 7, alpha=1.0, beta=0.0, C=None, native: bool = False,
+           moduli: int | None = None):
     """C <- alpha A @ B + beta C for row-major torch CUDA tensors (float64 or
-    complex128, 2-D, unit stride along rows).
+    complex128, 2-D, unit stride along rows). `moduli` selects the Ozaki-II
+    path with that many moduli instead of Ozaki-I with `slices` slices.
 
     A row-major m x k tensor is the column-major k x m matrix A^T, so the call
     computes C^T = B^T A^T in BLAS terms; the emulation is symmetric under this
@@ -388,6 +428,9 @@ def matmul(A, B, slices: int = 7, alpha=1.0, beta=0.0, C=None, native: bool = Fa
     if native:
         fn = ozaki_native_zgemm if cplx else ozaki_native_dgemm
         rc = fn("N", "N", n, m, k, alpha, B, ldb, A, lda, beta, C, ldc)
+    elif moduli is not None:
+        fn = ozaki2_zgemm if cplx else ozaki2_dgemm
+        rc = fn("N", "N", n, m, k, alpha, B, ldb, A, lda, beta, C, ldc, moduli)
     else:
         fn = ozaki_zgemm if cplx else ozaki_dgemm
         rc = fn("N", "N", n, m, k, alpha, B, ldb, A, lda, beta, C, ldc, slices)

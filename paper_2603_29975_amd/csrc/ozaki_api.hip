@@ -5,6 +5,8 @@
 //   fill (zero the exponent codes) -> scan op(A) rows, op(B) columns ->
 //   split both operands into packed INT8 slices -> fused slice GEMM with FP64
 //   recombination and alpha/beta.
+// An Ozaki-II call shares the fill and scan, then writes INT8 residue planes,
+// runs one batched INT8 GEMM over the moduli and rebuilds C by the CRT.
 // The interface mirrors a BLAS GEMM because the paper's solver reaches the
 // emulation through intercepted standard BLAS calls (Section 3.1).
 #include <algorithm>
@@ -17,6 +19,8 @@
 #include <list>
 #include <map>
 #include <vector>
+
+#include <rocblas/rocblas.h>
 
 #include "../../include/ozaki.h"
 #include "ozaki_internal.hpp"
@@ -399,6 +403,152 @@ int native_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64
   a.C = C;
   a.ldc = ldc;
   return hip_rc(launch_native(a, g.stream));
+}
+
+// ---------------------------------------------------------------- Ozaki-II
+// The N modular products are one plain strided-batched INT8 x INT8 -> INT32
+// library GEMM (rocBLAS); the integer conversion, residues and the CRT
+// rebuild are this library's kernels. One rocBLAS handle per device, bound to
+// the library's stream at every call.
+rocblas_handle g_blas[kMaxDev] = {};
+
+int blas_handle(int dev, rocblas_handle *h) {
+  if (g_blas[dev] == nullptr && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success) {
+    g_blas[dev] = nullptr;
+    return OZAKI_ERR_INTERNAL;
+  }
+  if (rocblas_set_stream(g_blas[dev], g.stream) != rocblas_status_success) return OZAKI_ERR_INTERNAL;
+  *h = g_blas[dev];
+  return OZAKI_OK;
+}
+
+// Workspace of one Ozaki-II product: exponent codes, the residue planes of A'
+// (N x m rows) and B' (N x n' rows), K' padded to 64 bytes per row, and the N
+// INT32 product planes (m x n').
+struct Plan2 {
+  int N, beta;
+  bool cplx;
+  int64_t m, n, k, kprime, kpad, nprime;
+  size_t off_codeA, off_codeB, off_RA, off_RB, off_C, total;
+};
+
+// 0, or the negative argument number of a size the path cannot take: -5 for
+// K' above OZAKI2_K_MAX, -14 for too few moduli (beta < 1), -3/-4 for
+// dimensions beyond the library GEMM's 32-bit sizes.
+int make_plan2(bool cplx, int64_t m, int64_t n, int64_t k, int N, Plan2 *p) {
+  *p = Plan2{};
+  p->N = N;
+  p->cplx = cplx;
+  p->m = m;
+  p->n = n;
+  p->k = k;
+  p->kprime = cplx ? 2 * k : k;
+  p->nprime = cplx ? 2 * n : n;
+  if (p->kprime > OZAKI2_K_MAX) return -5;
+  p->beta = crt_beta(N, std::max<int64_t>(p->kprime, 1));
+  if (p->beta < 1) return -14;
+  p->kpad = round_up(std::max<int64_t>(p->kprime, 1), 64);
+  if (m > 0x7fffffffll) return -3;
+  if (p->nprime > 0x7fffffffll) return -4;
+  size_t off = 0;
+  p->off_codeA = off;
+  off += align256(sizeof(int) * (size_t)std::max<int64_t>(m, 1));
+  p->off_codeB = off;
+  off += align256(sizeof(int) * (size_t)std::max<int64_t>(n, 1));
+  p->off_RA = off;
+  off += align256((size_t)N * m * p->kpad);
+  p->off_RB = off;
+  off += align256((size_t)N * p->nprime * p->kpad);
+  p->off_C = off;
+  off += align256(sizeof(int32_t) * (size_t)N * m * p->nprime);
+  p->total = off;
+  return 0;
+}
+
+int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                     double ar, double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                     double br, double bi, void *C, int64_t ldc, int moduli) {
+  int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
+  if (rc) return rc;
+  if (moduli < OZAKI2_MODULI_MIN || moduli > OZAKI2_MODULI_MAX) return -14;
+  if (m == 0 || n == 0) return OZAKI_OK;
+  if (C == nullptr) return -12;
+  const bool alpha_zero = ar == 0.0 && ai == 0.0;
+  const bool beta_zero = br == 0.0 && bi == 0.0;
+  const bool beta_one = br == 1.0 && bi == 0.0;
+  if (alpha_zero || k == 0) {
+    if (beta_one) return OZAKI_OK;
+    return hip_rc(launch_scale(cplx, m, n, br, bi, beta_zero, C, ldc, g.stream));
+  }
+  if (A == nullptr) return -7;
+  if (B == nullptr) return -9;
+  Plan2 p;
+  if ((rc = make_plan2(cplx, m, n, k, moduli, &p))) return rc;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  rocblas_handle h = nullptr;
+  if ((rc = blas_handle(dev, &h))) return rc;
+  void *wsv = nullptr;
+  if ((rc = get_workspace(p.total, &wsv))) return rc;
+  char *ws = static_cast<char *>(wsv);
+  int *codeA = reinterpret_cast<int *>(ws + p.off_codeA);
+  int *codeB = reinterpret_cast<int *>(ws + p.off_codeB);
+  int8_t *RA = reinterpret_cast<int8_t *>(ws + p.off_RA);
+  int8_t *RB = reinterpret_cast<int8_t *>(ws + p.off_RB);
+  int32_t *Ci = reinterpret_cast<int32_t *>(ws + p.off_C);
+  const View va = view_opA(A, transa, m, k, lda, cplx);
+  const View vb = view_opB(B, transb, k, n, ldb, cplx);
+  hipStream_t st = g.stream;
+
+  int mk = phase_begin(OZAKI_PHASE_SCAN, st);
+  if ((rc = hip_rc(launch_fill_i32(codeA, m, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(codeB, n, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(va, cplx, codeA, st)))) return rc;
+  if ((rc = hip_rc(launch_scan(vb, cplx, codeB, st)))) return rc;
+  phase_end(mk, st);
+
+  mk = phase_begin(OZAKI_PHASE_SPLIT, st);
+  const int64_t planeA = m * p.kpad, planeB = p.nprime * p.kpad;
+  if ((rc = hip_rc(launch_residues(va, cplx, false, codeA, moduli, p.beta, RA, p.kpad, planeA, st))))
+    return rc;
+  if ((rc = hip_rc(launch_residues(vb, cplx, true, codeB, moduli, p.beta, RB, p.kpad, planeB, st))))
+    return rc;
+  phase_end(mk, st);
+
+  // C_k (m x n', column-major) = RA_k^T RB_k with RA_k, RB_k stored K'-major.
+  mk = phase_begin(OZAKI_PHASE_GEMM, st);
+  const int32_t one = 1, zero = 0;
+  const int64_t planeC = m * p.nprime;
+  const rocblas_status bs = rocblas_gemm_strided_batched_ex(
+      h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m,
+      (rocblas_int)p.nprime, (rocblas_int)p.kpad, &one, RA, rocblas_datatype_i8_r,
+      (rocblas_int)p.kpad, (rocblas_stride)planeA, RB, rocblas_datatype_i8_r, (rocblas_int)p.kpad,
+      (rocblas_stride)planeB, &zero, Ci, rocblas_datatype_i32_r, (rocblas_int)m,
+      (rocblas_stride)planeC, Ci, rocblas_datatype_i32_r, (rocblas_int)m, (rocblas_stride)planeC,
+      (rocblas_int)moduli, rocblas_datatype_i32_r, rocblas_gemm_algo_standard, 0, 0);
+  phase_end(mk, st);
+  if (bs != rocblas_status_success) return OZAKI_ERR_HIP;
+
+  mk = phase_begin(OZAKI_PHASE_RECON, st);
+  CrtArgs ca{};
+  ca.Cint = Ci;
+  ca.plane = planeC;
+  ca.m = m;
+  ca.n = n;
+  ca.codeA = codeA;
+  ca.codeB = codeB;
+  ca.beta = p.beta;
+  ca.ar = ar;
+  ca.ai = ai;
+  ca.br = br;
+  ca.bi = bi;
+  ca.beta_zero = beta_zero ? 1 : 0;
+  ca.C = C;
+  ca.ldc = ldc;
+  rc = hip_rc(launch_crt(moduli, cplx, ca, st));
+  phase_end(mk, st);
+  if (g_tm.on) ++g_tm.calls;
+  return rc;
 }
 
 // View of op(X) for the debug hooks (see ozaki.h for `side`).
@@ -1250,6 +1400,44 @@ int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, ozaki
                        beta.im, C, ldc, slices);
 }
 
+int ozaki2_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                 double *C, int64_t ldc, int moduli) {
+  return ozaki2_gemm_impl(false, transa, transb, m, n, k, alpha, 0.0, A, lda, B, ldb, beta, 0.0, C,
+                          ldc, moduli);
+}
+
+int ozaki2_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, ozaki_z alpha,
+                 const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb, ozaki_z beta,
+                 ozaki_z *C, int64_t ldc, int moduli) {
+  return ozaki2_gemm_impl(true, transa, transb, m, n, k, alpha.re, alpha.im, A, lda, B, ldb,
+                          beta.re, beta.im, C, ldc, moduli);
+}
+
+int ozaki2_moduli(int moduli, int32_t *out) {
+  if (moduli < OZAKI2_MODULI_MIN || moduli > OZAKI2_MODULI_MAX) return -1;
+  if (out == nullptr) return -2;
+  for (int q = 0; q < moduli; ++q) out[q] = crt_modulus(q);
+  return OZAKI_OK;
+}
+
+int ozaki2_beta_bits(int moduli, int64_t kprime) {
+  if (moduli < OZAKI2_MODULI_MIN || moduli > OZAKI2_MODULI_MAX) return -1;
+  if (kprime < 1 || kprime > OZAKI2_K_MAX) return -2;
+  const int b = crt_beta(moduli, kprime);
+  return b < 1 ? 0 : b;
+}
+
+size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int moduli) {
+  kind = up(kind);
+  if ((kind != 'D' && kind != 'Z') || m < 0 || n < 0 || k < 0 || moduli < OZAKI2_MODULI_MIN ||
+      moduli > OZAKI2_MODULI_MAX)
+    return 0;
+  Plan2 p;
+  if (make_plan2(kind == 'Z', m, n, k, moduli, &p)) return 0;
+  return p.total;
+}
+
 int ozaki_native_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
                        const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                        double *C, int64_t ldc) {
@@ -1573,6 +1761,11 @@ int ozaki_finalize(void) {
   }
   g_sel.ws_bytes = 0;
   g_sel.plan_ws_bytes = 0;
+  for (int d = 0; d < kMaxDev; ++d) {
+    if (g_blas[d] == nullptr) continue;
+    if (rocblas_destroy_handle(g_blas[d]) != rocblas_status_success) rc = OZAKI_ERR_INTERNAL;
+    g_blas[d] = nullptr;
+  }
   return rc;
 }
 

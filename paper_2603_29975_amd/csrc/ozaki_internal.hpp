@@ -170,6 +170,35 @@ hipError_t launch_probe_max_batched(const ProbeTask *tasks, int ntasks, double *
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
                         int nv, uint64_t seed, void *ws, double *est, hipStream_t st);
 
+// Ozaki-II (see ozaki2.hip): N pairwise-coprime moduli, integer conversion
+// with beta bits per operand entry, INT8 residue planes, INT32 modular
+// products and the CRT rebuild.
+constexpr int kModMax = 20;
+// The k-th modulus (0-based; 0 outside 0..kModMax-1).
+int crt_modulus(int k);
+// floor(log2(m_0 ... m_{n-1})), or -1 for n outside 1..kModMax.
+int crt_log2_floor(int n);
+// beta = min(63, floor((floor(log2 M) - 1 - ceil(log2 K')) / 2)); below 1
+// means too few moduli for the contraction length.
+int crt_beta(int n, int64_t kprime);
+// Residues of X' (rows of op(A), or of B' for side_b) into n planes of
+// `plane` bytes, row-major with ldx bytes per row (ldx a multiple of 64, the
+// contraction entries K' <= l < ldx written as zero).
+hipError_t launch_residues(const View &v, bool cplx, bool side_b, const int *code, int n, int beta,
+                           int8_t *out, int64_t ldx, int64_t plane, hipStream_t st);
+struct CrtArgs {
+  const int32_t *Cint;  // n planes of m x n' INT32 products, column j' at Cint + j' m
+  int64_t plane;        // elements per plane
+  int64_t m, n;         // output rows and columns
+  const int *codeA, *codeB;
+  int beta;
+  double ar, ai, br, bi;
+  int beta_zero;
+  void *C;
+  int64_t ldc;
+};
+hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
+
 // Native FP64 matrix-core GEMM.
 struct NativeArgs {
   View A;  // op(A): rows i, contraction l

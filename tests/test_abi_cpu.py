@@ -18,7 +18,7 @@ def _declared_functions():
             continue
         text = open(os.path.join(ROOT, "include", fn)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ozaki_[a-z_0-9]+)\s*\(", text, flags=re.M)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ozaki2?_[a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -35,7 +35,7 @@ def test_binding_covers_every_declared_symbol():
         assert hasattr(oz, name), name
 
 
-@pytest.mark.parametrize("fn", ["ozaki_dgemm", "ozaki_zgemm"])
+@pytest.mark.parametrize("fn", ["ozaki_dgemm", "ozaki_zgemm", "ozaki2_dgemm", "ozaki2_zgemm"])
 def test_gemm_argument_errors(fn):
     f = getattr(oz, fn)
     ok = dict(transa="N", transb="N", m=4, n=5, k=6, alpha=1.0, A=0, lda=4, B=0, ldb=6, beta=0.0,
@@ -58,7 +58,9 @@ def test_gemm_argument_errors(fn):
     assert call(transb="C", ldb=4) == -10         # rows of B as stored = n = 5
     assert call(ldc=3) == -13
     assert call(slices=0) == -14
-    assert call(slices=13) == -14
+    assert call(slices=21 if fn.startswith("ozaki2") else 13) == -14
+    if fn.startswith("ozaki2"):
+        assert call(slices=1) == -14
     assert call(C=0) == -12                       # null C with work to do
     assert call(m=0) == 0 and call(n=0) == 0      # quick returns, nothing launched
     assert call(A=0, C=1 << 40) == -7             # null A with alpha != 0 and k > 0
@@ -170,3 +172,38 @@ def test_tuning_table_host_logic():
     assert rc == -6 and best == -1
     assert oz.ozaki_autotune("x", 8, 8, 8, 7)[0] == -1
     assert oz.ozaki_tune_save(None) == -1 and oz.ozaki_tune_load(None) == -1
+
+
+def test_ozaki2_host_logic_matches_the_oracle():
+    # moduli and the bit budget beta: the library's host tables against the
+    # oracle's definitions (reading Q1/Q2), without device work
+    from oracle import ozaki2
+    for n in range(oz.MODULI_MIN, oz.MODULI_MAX + 1):
+        rc, mods = oz.ozaki2_moduli(n)
+        assert rc == 0 and mods == ozaki2.moduli(n)
+        for kp in (1, 2, 3, 64, 100, 4096, 4097, 65536, 131072):
+            try:
+                want = ozaki2.beta_bits(n, kp)
+            except ValueError:
+                want = 0
+            assert oz.ozaki2_beta_bits(n, kp) == want, (n, kp)
+    assert oz.ozaki2_moduli(1)[0] == -1 and oz.ozaki2_moduli(21)[0] == -1
+    assert oz.ozaki2_beta_bits(14, 0) == -2 and oz.ozaki2_beta_bits(14, oz.K2_MAX + 1) == -2
+
+
+def test_ozaki2_size_limits_and_workspace():
+    big = 1 << 40
+    # K' beyond exact INT32 modular sums: k for real, 2k for complex
+    assert oz.ozaki2_dgemm("N", "N", 4, 4, oz.K2_MAX + 1, 1.0, big, 4, big, oz.K2_MAX + 1, 0.0,
+                           big, 4, 14) == -5
+    assert oz.ozaki2_zgemm("N", "N", 4, 4, oz.K2_MAX // 2 + 1, 1.0, big, 4, big,
+                           oz.K2_MAX // 2 + 1, 0.0, big, 4, 14) == -5
+    # two moduli leave no bits for K' = 2^13 (beta < 1)
+    assert oz.ozaki2_dgemm("N", "N", 4, 4, 8192, 1.0, big, 4, big, 8192, 0.0, big, 4, 2) == -14
+    assert oz.ozaki2_workspace_bytes("d", 4, 4, 8192, 2) == 0
+    assert oz.ozaki2_workspace_bytes("z", 4, 4, oz.K2_MAX, 14) == 0
+    w14 = oz.ozaki2_workspace_bytes("z", 256, 256, 256, 14)
+    # residues of A' (256 x 512) and B' (512 x 512) and INT32 products (256 x 512) per modulus
+    assert w14 >= 14 * (256 * 512 + 512 * 512 + 4 * 256 * 512)
+    assert oz.ozaki2_workspace_bytes("z", 256, 256, 256, 16) > w14
+    assert oz.ozaki2_workspace_bytes("q", 4, 4, 4, 14) == 0
