@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--moduli", type=int, default=None,
+                    help="run the Ozaki-II (CRT) path with this many moduli instead of Ozaki-I")
     ap.add_argument("--workload", default="kkr2048",
                     choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512",
                              "selector512"])
@@ -143,17 +145,21 @@ def main():
     kind = wl["kind"]
     m, k = A.shape
     n = B.shape[1]
-    s = args.slices
+    ozaki2 = args.moduli is not None
+    s = args.moduli if ozaki2 else args.slices
     cplx = kind == "z"
     tdt = torch.complex128 if cplx else torch.float64
-    log(f"workload {wl['name']} m={m} n={n} k={k} s={s}")
+    log(f"workload {wl['name']} m={m} n={n} k={k} " + (f"moduli={s}" if ozaki2 else f"s={s}"))
 
     # Column-major device operands: the row-major tensor of X^T is X column-major.
     Ad = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev)
     Bd = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
     Cd = torch.zeros((n, m), dtype=tdt, device=dev)
     Cn = torch.zeros((n, m), dtype=tdt, device=dev)
-    gemm = oz.ozaki_zgemm if cplx else oz.ozaki_dgemm
+    if ozaki2:
+        gemm = oz.ozaki2_zgemm if cplx else oz.ozaki2_dgemm
+    else:
+        gemm = oz.ozaki_zgemm if cplx else oz.ozaki_dgemm
     native = oz.ozaki_native_zgemm if cplx else oz.ozaki_native_dgemm
 
     def run_ozaki(slices=s, out=Cd):
@@ -167,11 +173,11 @@ def main():
             raise RuntimeError(f"{native.__name__}: {oz.ozaki_status_string(rc)}")
 
     flops = (8.0 if cplx else 2.0) * m * n * k          # effective FP64 flops per call
-    pairs = s * (s + 1) // 2
+    pairs = s if ozaki2 else s * (s + 1) // 2            # INT8 products: moduli or slice pairs
     int8_ops = pairs * flops                             # INT8 ops of the slice GEMM per call
 
     # ---------------------------------------------------------------- emulation
-    tuning = select_tiles(oz, args.tune, kind, m, n, k, s)
+    tuning = None if ozaki2 else select_tiles(oz, args.tune, kind, m, n, k, s)
     for _ in range(args.warmup):
         run_ozaki()
     torch.cuda.synchronize()
@@ -194,12 +200,17 @@ def main():
 
     gemm_ms = phases["gemm"]
     achieved = int8_ops / (gemm_ms * 1e-3) / 1e12
-    traffic = read_traffic(tuning["tune_id"])
+    if ozaki2:
+        kernel = (f"batched INT8 GEMM over {s} moduli (rocBLAS strided-batched, i8 x i8 -> i32); "
+                  "residue and CRT kernels are timed in phases_ms")
+        traffic = None
+    else:
+        kernel = ("fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
+                  f"{tuning['tune_id']})")
+        traffic = read_traffic(tuning["tune_id"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-                "traffic": traffic,
-                "kernel": "fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
-                          f"{tuning['tune_id']})",
+                "traffic": traffic, "kernel": kernel,
                 "ops_per_launch": int8_ops, "avg_launch_ms": round(gemm_ms, 4),
                 "note": "INT8 MFMA work counted as 2 ops per multiply-add against the "
                         "5000 TOP/s dense INT8 peak"}
@@ -233,7 +244,7 @@ def main():
     cpu = None
     accuracy = None
     if not args.no_cpu_baseline:
-        cpu, accuracy = cpu_leg(wl, s, Cd, m, n, k, run_ozaki, args.cpu_seconds)
+        cpu, accuracy = cpu_leg(wl, s, Cd, m, n, k, run_ozaki, args.cpu_seconds, ozaki2)
 
     out = {
         "metric": METRIC,
@@ -249,8 +260,11 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": wl["name"], "m": m, "n": n, "k": k,
-                   "operands": "complex128" if cplx else "float64", "slices": s,
-                   "pairs": pairs, "seed": wl["seed"], "inputs": wl["desc"]},
+                   "operands": "complex128" if cplx else "float64",
+                   "method": "ozaki2" if ozaki2 else "ozaki1",
+                   ("moduli" if ozaki2 else "slices"): s,
+                   ("int8_products" if ozaki2 else "pairs"): pairs,
+                   "seed": wl["seed"], "inputs": wl["desc"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "native_fp64": native_rec,
@@ -408,13 +422,16 @@ def run_selector(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
+def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False):
     """The oracle timed on a bounded sample (rows 0..ms-1 of op(A) against the
     whole op(B)), plus the accuracy check of the GPU result on sampled entries
-    against the oracle's double-double reference."""
+    against the oracle's double-double reference. `s` is the slice count, or
+    the moduli count of the Ozaki-II path."""
     import numpy as np
     import torch
     from oracle import dd, metrics, ozaki
+    from oracle import ozaki2 as ozaki2_model
+    model = ozaki2_model.ozaki2_gemm if ozaki2 else ozaki.ozaki_gemm
     threads = blas_threads()
     A, B = wl["A"], wl["B"]
     torch.cuda.synchronize()
@@ -428,7 +445,7 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
     den = metrics.denom_entries("N", "N", A, B, ri, cj)
     err_s = metrics.err_comp(C[ri, cj], hi, lo, den)
     err_prev = None
-    if s > 1:
+    if s > (2 if ozaki2 else 1):
         Cprev = torch.zeros_like(Cd)
         run_ozaki(s - 1, Cprev)
         torch.cuda.synchronize()
@@ -437,15 +454,39 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s):
     # bit-exact spot check against the oracle model on 8 rows x 8 columns
     rs = np.sort(rng.choice(m, 8, replace=False))
     cs = np.sort(rng.choice(n, 8, replace=False))
-    ref = ozaki.ozaki_gemm("N", "N", A[rs], B[:, cs], s)
+    ref = model("N", "N", A[rs], B[:, cs], s)
     exact = bool(np.array_equal(C[np.ix_(rs, cs)].view(np.uint64), ref.view(np.uint64)))
     accuracy = {"err_comp_sampled": err_s, "err_comp_sampled_s_minus_1": err_prev,
                 "entries": 1024, "reference": "double-double (oracle)",
                 "target": 1e-12, "meets_target": bool(err_s <= 1e-12),
                 "oracle_bit_exact_8x8": exact}
-    log(f"accuracy: err_comp(s={s}) {err_s:.3e}  (s-1) {err_prev}  bit-exact 8x8 {exact}")
+    log(f"accuracy: err_comp({s}) {err_s:.3e}  ({s - 1}) {err_prev}  bit-exact 8x8 {exact}")
 
     # oracle timing on a bounded sample
+    if ozaki2:
+        # the integer model converts every entry of its operands with Python
+        # integers, so the sample is a square block: rows 0..r-1 of op(A)
+        # against columns 0..r-1 of op(B), over the whole contraction
+        def timed_block(r):
+            t0 = time.perf_counter()
+            model("N", "N", A[:r], B[:, :r], s)
+            return time.perf_counter() - t0
+
+        r = 4
+        t = timed_block(r)
+        while t < target_s / 2 and r < min(m, n):
+            r = min(2 * r, m, n)
+            t = timed_block(r)
+        flops = (8.0 if np.iscomplexobj(A) else 2.0) * r * r * k
+        cpu = {"value": round(flops / t / 1e12, 9), "unit": "TFLOP/s", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"oracle Ozaki-II model (Python integers, numpy residue products) on rows "
+                         f"0..{r - 1} of op(A) against columns 0..{r - 1} of op(B): {r}x{r}x{k}, "
+                         f"moduli={s}, {t:.2f} s",
+               "host_cpus": os.cpu_count()}
+        log(f"cpu oracle: {cpu}")
+        return cpu, accuracy
+
     def timed(rows):
         t0 = time.perf_counter()
         ozaki.ozaki_gemm("N", "N", A[:rows], B, s)

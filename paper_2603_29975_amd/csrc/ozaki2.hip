@@ -30,13 +30,25 @@ namespace crt {
 
 // ---------------------------------------------------------------- constants
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+constexpr int kLimbs = 11;  // 16-bit limbs of the products P_k (< 2^160)
 
 struct Tables {
-  int m[kModMax];             // the moduli, greedy from 256 downwards
-  int pm[kModMax][kModMax];   // pm[j][q] = (m_0 ... m_{j-1}) mod m_q
-  int inv[kModMax];           // inverse of (m_0 ... m_{k-1}) mod m_k
-  int pw[kModMax][4];         // 2^(16 t) mod m_k
+  int m[kModMax];            // the moduli, greedy from 256 downwards
+  int inv[kModMax];          // (P_k)^-1 mod m_k, P_k = m_0 ... m_{k-1} (balanced)
+  int g[kModMax][kModMax];   // g[j][q] = P_j (P_q)^-1 mod m_q for j < q (balanced)
+  int ng[(kModMax + 3) / 4][kModMax];  // -g[4 h + b][q] as bytes b of a word (0 for 4 h + b >= q)
+  int pw[kModMax][5];        // 2^(13 t) mod m_k (balanced)
+  int c13[kModMax][3];       // 2^(13 t) (P_k)^-1 mod m_k (balanced)
+  int P[kModMax][kLimbs];    // 16-bit limbs of P_k
+  int nl[kModMax];           // nonzero limbs of P_k
+  int nlM[kModMax + 1];      // limbs of M_n = P_n plus a sign limb
 };
+
+constexpr int bal_c(int r, int m) {
+  r %= m;
+  if (r < 0) r += m;
+  return r >= (m + 1) / 2 ? r - m : r;
+}
 
 constexpr Tables make_tables() {
   Tables t{};
@@ -47,22 +59,50 @@ constexpr Tables make_tables() {
       if (gcd_c(c, t.m[j]) != 1) ok = false;
     if (ok) t.m[n++] = c;
   }
+  int pmod[kModMax][kModMax] = {};  // P_j mod m_q
   for (int q = 0; q < kModMax; ++q) {
     int p = 1 % t.m[q];
     for (int j = 0; j < kModMax; ++j) {
-      t.pm[j][q] = p;  // product of the moduli before j, mod m_q
+      pmod[j][q] = p;
       p = (p * t.m[j]) % t.m[q];
     }
   }
   for (int k = 0; k < kModMax; ++k) {
-    const int a = t.pm[k][k];
+    const int mk = t.m[k];
     int x = 1;
-    while ((a * x) % t.m[k] != 1 % t.m[k]) ++x;
-    t.inv[k] = x % t.m[k];
+    while ((pmod[k][k] * x) % mk != 1 % mk) ++x;
+    t.inv[k] = bal_c(x, mk);
+    for (int j = 0; j < k; ++j) t.g[j][k] = bal_c(pmod[j][k] * x, mk);
+    for (int h = 0; h < (kModMax + 3) / 4; ++h) {
+      unsigned w = 0;
+      for (int b = 0; b < 4; ++b)
+        if (4 * h + b < k) w |= (unsigned)(-t.g[4 * h + b][k] & 0xff) << (8 * b);
+      t.ng[h][k] = (int)w;
+    }
     int w = 1;
-    for (int s = 0; s < 4; ++s) {
-      t.pw[k][s] = w % t.m[k];
-      for (int b = 0; b < 16; ++b) w = (w * 2) % t.m[k];
+    for (int s = 0; s < 5; ++s) {
+      t.pw[k][s] = bal_c(w, mk);
+      if (s < 3) t.c13[k][s] = bal_c(w * x, mk);
+      for (int b = 0; b < 13; ++b) w = (w * 2) % mk;
+    }
+  }
+  int limb[kLimbs] = {1};
+  for (int k = 0; k <= kModMax; ++k) {
+    int top = 0;
+    for (int l = 0; l < kLimbs; ++l)
+      if (limb[l] != 0) top = l + 1;
+    if (k < kModMax) {
+      for (int l = 0; l < kLimbs; ++l) t.P[k][l] = limb[l];
+      t.nl[k] = top;
+    }
+    // limbs of M_k (bits up to 16 top) plus one more for the sign of values in [-M/2, M/2)
+    t.nlM[k] = top + 1 > kLimbs ? kLimbs : top + 1;
+    if (k == kModMax) break;
+    int carry = 0;
+    for (int l = 0; l < kLimbs; ++l) {
+      const int v = limb[l] * t.m[k] + carry;
+      limb[l] = v & 0xffff;
+      carry = v >> 16;
     }
   }
   return t;
@@ -71,147 +111,160 @@ constexpr Tables make_tables() {
 constexpr Tables kT = make_tables();
 static_assert(kT.m[0] == 256 && kT.m[1] == 255 && kT.m[11] == 217 && kT.m[19] == 173,
               "greedy coprime moduli");
+static_assert(kT.nlM[kModMax] <= kLimbs, "limb count of the largest modulus product");
 
-// x mod m in [0, m) for a 32-bit value. m = 256 reads the low byte, which is
-// also right for INT32 sums that wrapped around.
+// Balanced residue of t modulo an odd m_K for |t| < 2^22: q = rint(t / m)
+// computed in FP32 is the exact nearest quotient. t converts exactly, the
+// quotient carries a relative error below 2^-23 (below 1/(2m) in absolute
+// terms for |t| < 2^22), while t/m stays at least 1/(2m) away from every
+// half-integer because m is odd. So r = t - q m is the balanced residue in
+// [-(m-1)/2, (m-1)/2] without a correction step; every operation is a
+// full-rate FP32 or 24-bit integer instruction.
 template <int K>
-__device__ __forceinline__ int mod_pos(int x) {
+__device__ __forceinline__ int bal_mod(int t) {
   constexpr int m = kT.m[K];
-  if constexpr (m == 256) {
-    return x & 255;
-  } else {
-    int r = x % m;
-    return r < 0 ? r + m : r;
-  }
-}
-
-// Balanced representative of r in [0, m).
-template <int K>
-__device__ __forceinline__ int balance(int r) {
-  constexpr int m = kT.m[K];
-  return r >= (m + 1) / 2 ? r - m : r;
+  static_assert(m % 2 == 1, "odd moduli only");
+  constexpr float rm = 1.0f / (float)m;
+  const int q = (int)__builtin_rintf((float)t * rm);
+  return t - __mul24(q, m);
 }
 
 // ---------------------------------------------------------------- residues
-// Residue tile: 64 rows of X' x 64 contraction entries. Rows of X' are view
-// rows, except for complex B where X' rows 2j and 2j+1 both come from view
-// row j (32 view rows per tile).
-template <bool CPLX, bool SIDEB>
-struct ResTile {
-  static constexpr int TR = (CPLX && SIDEB) ? 32 : 64;  // view rows
-  static constexpr int TL = CPLX ? 32 : 64;              // contraction elements
-  static constexpr int EW = CPLX ? 2 : 1;                // doubles per element
-  static constexpr int PITCH = TL * EW + 1;              // doubles per LDS row
-};
-constexpr int kResTileDoubles = 64 * (64 + 1);
+// Residue tile: 16 view rows x 128 contraction entries of X' (64 complex
+// elements); for complex B the 16 view rows (columns j) give the 32 X' rows
+// 2j = (Re, -Im) and 2j+1 = (Im, Re). A thread converts 8 consecutive entries
+// of one row, so the 16 threads of a row write its 128 residue bytes of one
+// modulus as one full 128-byte line. In LDS entry e of a row sits at
+// e + e / 8 (one pad double per 8), which spreads the 16 threads of a row
+// over distinct banks.
+constexpr int kResRows = 16;
+constexpr int kResEntries = 128;
+constexpr int kResPitch = kResEntries + kResEntries / 8 + 1;  // doubles per LDS row
+constexpr int kResTileDoubles = kResRows * kResPitch;
+__device__ __forceinline__ int res_slot(int e) { return e + (e >> 3); }
 
-// |x| 2^(beta - e) truncated, as an unsigned integer (< 2^63), and the sign.
-__device__ __forceinline__ uint64_t to_int(double x, int e, int beta, bool &neg) {
+// trunc(x 2^(beta - e)) as five signed 13-bit pieces: x' = sum_t a_t 2^(13 t)
+// with every a_t carrying the sign of x (|x'| < 2^63, so a_4 < 2^11).
+constexpr int kPieces = 5;
+__device__ __forceinline__ void to_pieces(double x, int e, int beta, int (&a)[kPieces]) {
   const Sig s = decompose(x, e);
-  neg = s.neg;
   const int sh = s.sh0 + beta;
-  if (sh >= 0) return s.m << sh;  // |x| < 2^e: the result stays below 2^beta
-  return sh > -64 ? (s.m >> (-sh)) : 0ull;
-}
-
-// Balanced residue of +-u modulo m_K from the 16-bit pieces of u.
-template <int K>
-__device__ __forceinline__ int residue(const uint32_t (&a)[4], bool neg) {
-  constexpr int m = kT.m[K];
-  uint32_t t = a[0];
-  if constexpr (m != 256)
-    t += a[1] * (uint32_t)kT.pw[K][1] + a[2] * (uint32_t)kT.pw[K][2] +
-         a[3] * (uint32_t)kT.pw[K][3];  // < 2^16 (1 + 3 * 255) < 2^26
-  int r = (int)(t % (uint32_t)m);
-  if (neg && r != 0) r = m - r;
-  return balance<K>(r);
-}
-
-template <int N, int K>
-__device__ __forceinline__ void store_residues(const uint32_t (&a)[16][4], const bool (&neg)[16],
-                                               int8_t *dst, int64_t plane) {
-  if constexpr (K < N) {
-    uint32_t w[4];
+  uint64_t u;
+  if (sh >= 0)
+    u = s.m << sh;  // |x| < 2^e: the result stays below 2^beta
+  else
+    u = sh > -64 ? (s.m >> (-sh)) : 0ull;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t word = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        word |= ((uint32_t)residue<K>(a[4 * q + b], neg[4 * q + b]) & 0xffu) << (8 * b);
-      w[q] = word;
-    }
-    *reinterpret_cast<uint4 *>(dst + (int64_t)K * plane) = make_uint4(w[0], w[1], w[2], w[3]);
-    store_residues<N, K + 1>(a, neg, dst, plane);
+  for (int t = 0; t < kPieces; ++t) {
+    const int v = (int)((u >> (13 * t)) & 0x1fffu);
+    a[t] = s.neg ? -v : v;
   }
 }
 
-// One block: X' rows [64 bx, 64 bx + 64) x contraction entries [64 by, 64 by
-// + 64). The tile is first copied into LDS with consecutive threads on the
-// unit-stride direction of the view; thread t then converts the 16 entries
-// [16 (t % 4), +16) of X' row 64 bx + t / 4 and writes their N residues, one
-// 16-byte store per modulus into plane k (row-major, `ldx` bytes per row).
+// Balanced residue of x' modulo m_K from its signed pieces:
+// x' = sum a_t 2^(13 t) = sum a_t pw_t (mod m) with |pw_t| <= 127, so the sum
+// stays below 8191 * (1 + 4 * 127) < 2^22 and bal_mod is exact. For m = 256
+// the residue is the low byte of x' in two's complement, which is the low
+// byte of a_0 (2^13 = 0 mod 256).
+template <int K>
+__device__ __forceinline__ int residue(const int (&a)[kPieces]) {
+  if constexpr (kT.m[K] == 256) {
+    return a[0];  // only its low byte is stored
+  } else {
+    int t = a[0];
+#pragma unroll
+    for (int p = 1; p < kPieces; ++p) t += __mul24(a[p], kT.pw[K][p]);
+    return bal_mod<K>(t);
+  }
+}
+
+__device__ __forceinline__ uint32_t pack4(int r0, int r1, int r2, int r3) {
+  return (uint32_t)(r0 & 0xff) | ((uint32_t)(r1 & 0xff) << 8) | ((uint32_t)(r2 & 0xff) << 16) |
+         ((uint32_t)(r3 & 0xff) << 24);
+}
+
+// Residues of 16 consecutive contraction entries of one X' row, one 16-byte
+// store per modulus.
+template <int N, int K>
+__device__ __forceinline__ void store_residues(const int (&a)[8][kPieces], int8_t *dst, int64_t plane) {
+  if constexpr (K < N) {
+    int r[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) r[x] = residue<K>(a[x]);
+    *reinterpret_cast<uint2 *>(dst + (int64_t)K * plane) =
+        make_uint2(pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]));
+    store_residues<N, K + 1>(a, dst, plane);
+  }
+}
+
+// Complex B: the residues of 4 elements (Re, Im) give both X' rows: row 2j
+// holds (Re, -Im) and row 2j+1 holds (Im, Re) along the contraction. The
+// residue of -x is the negated residue (odd moduli: the balanced range is
+// symmetric; 256: bytes negate modulo 256).
+template <int N, int K>
+__device__ __forceinline__ void store_residues_b(const int (&a)[8][kPieces], int8_t *dst0,
+                                                 int8_t *dst1, int64_t plane) {
+  if constexpr (K < N) {
+    int r[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) r[x] = residue<K>(a[x]);  // r[2e] = Re, r[2e+1] = Im
+    *reinterpret_cast<uint2 *>(dst0 + (int64_t)K * plane) =
+        make_uint2(pack4(r[0], -r[1], r[2], -r[3]), pack4(r[4], -r[5], r[6], -r[7]));
+    *reinterpret_cast<uint2 *>(dst1 + (int64_t)K * plane) =
+        make_uint2(pack4(r[1], r[0], r[3], r[2]), pack4(r[5], r[4], r[7], r[6]));
+    store_residues_b<N, K + 1>(a, dst0, dst1, plane);
+  }
+}
+
+// One block: view rows [16 bx, 16 bx + 16) x contraction entries [128 by,
+// 128 by + 128) of X'. The tile is first copied into LDS with consecutive
+// threads on the unit-stride direction of the view; thread t then converts
+// the 8 entries [8 (t % 16), +8) of view row 16 bx + t / 16 and writes their
+// N residues into plane k (row-major, `ldx` bytes per X' row).
 template <bool CPLX, bool SIDEB, int N>
 __global__ void __launch_bounds__(256) k_residues(View v, const int *code, int beta, int8_t *out,
                                                   int64_t ldx, int64_t plane) {
-  using T = ResTile<CPLX, SIDEB>;
+  constexpr int TL = CPLX ? kResEntries / 2 : kResEntries;  // view elements per tile row
   __shared__ double tile[kResTileDoubles];
   const int64_t bx = blockIdx.x, by = blockIdx.y;
-  const int64_t r0 = bx * T::TR, l0 = by * T::TL;
+  const int64_t r0 = bx * kResRows, l0 = by * TL;
   const bool rows_fast = v.sr == 1 && v.sl != 1;
-  for (int c = threadIdx.x; c < T::TR * T::TL; c += 256) {
-    const int rr = rows_fast ? c % T::TR : c / T::TL;
-    const int ll = rows_fast ? c / T::TR : c % T::TL;
+  for (int c = threadIdx.x; c < kResRows * TL; c += 256) {
+    const int rr = rows_fast ? c % kResRows : c / TL;
+    const int ll = rows_fast ? c / kResRows : c % TL;
     const int64_t r = r0 + rr, l = l0 + ll;
     const bool in = r < v.R && l < v.L;
     if constexpr (CPLX) {
       double2 z = make_double2(0.0, 0.0);
       if (in) z = reinterpret_cast<const double2 *>(v.base)[r * v.sr + l * v.sl];
-      tile[rr * T::PITCH + 2 * ll] = z.x;
-      tile[rr * T::PITCH + 2 * ll + 1] = v.conj ? -z.y : z.y;
+      tile[rr * kResPitch + res_slot(2 * ll)] = z.x;
+      tile[rr * kResPitch + res_slot(2 * ll + 1)] = v.conj ? -z.y : z.y;
     } else {
-      tile[rr * T::PITCH + ll] = in ? reinterpret_cast<const double *>(v.base)[r * v.sr + l * v.sl] : 0.0;
+      tile[rr * kResPitch + res_slot(ll)] =
+          in ? reinterpret_cast<const double *>(v.base)[r * v.sr + l * v.sl] : 0.0;
     }
   }
   __syncthreads();
 
   const int tid = threadIdx.x;
-  const int orow = tid >> 2;                    // X' row within the tile
-  const int kq0 = (tid & 3) * 16;               // first contraction entry within the tile
-  const int64_t rp = bx * 64 + orow;
-  const int64_t rows = (CPLX && SIDEB) ? 2 * v.R : v.R;
-  if (rp >= rows) return;
-  const int trow = (CPLX && SIDEB) ? (orow >> 1) : orow;  // LDS row
-  const int64_t vr = (CPLX && SIDEB) ? (rp >> 1) : rp;    // view row
+  const int trow = tid >> 4;                    // view row within the tile
+  const int kq0 = (tid & 15) * 8;               // first contraction entry within the tile
+  const int64_t vr = bx * kResRows + trow;
+  if (vr >= v.R) return;
   const int c = code[vr];
   const bool live = !code_bad(c);
   const int e = code_exp(c);
 
-  uint32_t a[16][4];
-  bool neg[16];
+  int a[8][kPieces];
 #pragma unroll
-  for (int x = 0; x < 16; ++x) {
-    double val = 0.0;
-    if (live) {
-      if constexpr (CPLX && SIDEB) {
-        const int ll = (kq0 + x) >> 1;            // element of column j
-        const double re = tile[trow * T::PITCH + 2 * ll];
-        const double im = tile[trow * T::PITCH + 2 * ll + 1];
-        if ((rp & 1) == 0)
-          val = (x & 1) ? -im : re;               // row 2j: (Re, -Im)
-        else
-          val = (x & 1) ? re : im;                // row 2j+1: (Im, Re)
-      } else {
-        val = tile[trow * T::PITCH + kq0 + x];    // real, or (Re, Im) interleaved
-      }
-    }
-    const uint64_t u = to_int(val, e, beta, neg[x]);
-    a[x][0] = (uint32_t)(u & 0xffffu);
-    a[x][1] = (uint32_t)((u >> 16) & 0xffffu);
-    a[x][2] = (uint32_t)((u >> 32) & 0xffffu);
-    a[x][3] = (uint32_t)(u >> 48);
+  for (int x = 0; x < 8; ++x)
+    to_pieces(live ? tile[trow * kResPitch + res_slot(kq0 + x)] : 0.0, e, beta, a[x]);
+  if constexpr (CPLX && SIDEB) {
+    int8_t *dst0 = out + (2 * vr) * ldx + by * kResEntries + kq0;
+    store_residues_b<N, 0>(a, dst0, dst0 + ldx, plane);
+  } else {
+    store_residues<N, 0>(a, out + vr * ldx + by * kResEntries + kq0, plane);
   }
-  int8_t *dst = out + rp * ldx + by * 64 + kq0;
-  store_residues<N, 0>(a, neg, dst, plane);
 }
 
 // ---------------------------------------------------------------- reconstruction
@@ -220,27 +273,8 @@ struct I192 {
   uint64_t w0, w1, w2;
 };
 
-// x <- x * mul + d for 0 < mul <= 256 and a small signed d.
-__device__ __forceinline__ void mul_add(I192 &x, uint64_t mul, int d) {
-  const uint64_t lo0 = x.w0 * mul, hi0 = __umul64hi(x.w0, mul);
-  const uint64_t lo1 = x.w1 * mul, hi1 = __umul64hi(x.w1, mul);
-  const uint64_t lo2 = x.w2 * mul;
-  uint64_t r1 = lo1 + hi0;
-  uint64_t r2 = lo2 + hi1 + (r1 < lo1 ? 1u : 0u);
-  const uint64_t dd = (uint64_t)(int64_t)d, ext = d < 0 ? ~0ull : 0ull;
-  const uint64_t r0 = lo0 + dd;
-  const uint64_t c0 = r0 < lo0 ? 1u : 0u;
-  const uint64_t s1 = r1 + ext;
-  const uint64_t c1 = s1 < r1 ? 1u : 0u;
-  const uint64_t t1 = s1 + c0;
-  const uint64_t c2 = t1 < s1 ? 1u : 0u;
-  x.w0 = r0;
-  x.w1 = t1;
-  x.w2 = r2 + ext + c1 + c2;
-}
-
 // Round-to-nearest-even FP64 value of a 192-bit integer (its magnitude stays
-// below 2^160, so the result is finite and exact scaling applies).
+// below 2^160, so the result is finite and the final scaling exact).
 __device__ __forceinline__ double to_double_rn(I192 x) {
   const bool neg = (int64_t)x.w2 < 0;
   if (neg) {
@@ -271,12 +305,13 @@ __device__ __forceinline__ double to_double_rn(I192 x) {
     bool sticky = false;
     if (sh <= 0) {
       top = x.w0 << (-sh);
+    } else if (sh < 64) {
+      top = sh ? ((x.w0 >> sh) | (x.w1 << (64 - sh))) : x.w0;
+      sticky = (x.w0 << (64 - sh)) != 0;
     } else {
-      const int q = sh >> 6, b = sh & 63;
-      const uint64_t w[4] = {x.w0, x.w1, x.w2, 0ull};
-      top = b ? ((w[q] >> b) | (w[q + 1] << (64 - b))) : w[q];
-      for (int t = 0; t < q; ++t) sticky |= w[t] != 0;
-      if (b) sticky |= (w[q] << (64 - b)) != 0;
+      const int b = sh - 64;
+      top = b ? ((x.w1 >> b) | (x.w2 << (64 - b))) : x.w1;
+      sticky = x.w0 != 0 || (b && (x.w1 << (64 - b)) != 0);
     }
     uint64_t mant = top >> 11;  // 53 bits
     const bool rbit = (top >> 10) & 1u;
@@ -287,36 +322,67 @@ __device__ __forceinline__ double to_double_rn(I192 x) {
   return neg ? -r : r;
 }
 
-// Mixed-radix digits of c (Garner, balanced digits): d_K = (C_K - sum_{j<K}
-// d_j P_j) P_K^-1 mod m_K with P_j = m_0 ... m_{j-1}. acc[q] carries
-// sum_{j<K} d_j (P_j mod m_q) for the moduli still to come; its magnitude
-// stays below 20 * 128 * 256 < 2^20, so no reduction is needed on the way.
+// Mixed-radix digits of c (Garner, balanced digits):
+// d_K = (C_K - sum_{j<K} d_j P_j) P_K^-1 mod m_K. With C_K split into 13-bit
+// pieces c_0 + c_1 2^13 + c_2 2^26 (c_2 signed, |c_2| <= 32),
+// t = sum_p c_p (2^(13 p) P_K^-1) - sum_j d_j (P_j P_K^-1) is congruent to d_K
+// and below 2 * 8191 * 127 + 32 * 127 + 20 * 128 * 127 < 2^22 in magnitude
+// (balanced constants), so one exact bal_mod gives the digit. The digits are
+// kept as bytes of W (d_j in byte j % 4 of W[j / 4]), so the sum over the
+// earlier digits is one 4-way INT8 dot product per word.
 template <int N, int K>
-__device__ __forceinline__ void digits(const int (&Ck)[N], int (&acc)[N], int (&d)[N]) {
+__device__ __forceinline__ void digits(const int (&Ck)[N], int (&W)[(N + 3) / 4], int (&d)[N]) {
   if constexpr (K < N) {
-    constexpr int m = kT.m[K];
-    const int t = mod_pos<K>(mod_pos<K>(Ck[K]) - acc[K]);
-    const int dk = balance<K>((t * kT.inv[K]) % m);
-    d[K] = dk;
+    int dk;
+    if constexpr (K == 0) {
+      dk = (int)(int8_t)(Ck[0] & 0xff);  // m_0 = 256: INT32 wrap-around keeps the low byte
+      W[0] = Ck[0] & 0xff;
+    } else {
+      const int c0 = Ck[K] & 0x1fff, c1 = (Ck[K] >> 13) & 0x1fff, c2 = Ck[K] >> 26;
+      int t = c0 * kT.c13[K][0] + __mul24(c1, kT.c13[K][1]) + __mul24(c2, kT.c13[K][2]);
 #pragma unroll
-    for (int q = K + 1; q < N; ++q) acc[q] += dk * kT.pm[K][q];
-    digits<N, K + 1>(Ck, acc, d);
+      for (int h = 0; h <= (K - 1) / 4; ++h) t = __builtin_amdgcn_sdot4(W[h], kT.ng[h][K], t, false);
+      dk = bal_mod<K>(t);
+      if constexpr ((K & 3) == 0)
+        W[K >> 2] = dk & 0xff;
+      else
+        W[K >> 2] |= (dk & 0xff) << (8 * (K & 3));
+    }
+    d[K] = dk;
+    digits<N, K + 1>(Ck, W, d);
   }
 }
 
 // The integer c in [-M/2, M/2) with c = C_k mod m_k for k < N:
-// c = d_0 + m_0 (d_1 + m_1 (d_2 + ...)) evaluated in 192-bit arithmetic.
+// c = sum_k d_k P_k accumulated in 16-bit limbs (|partial| < 2^28), one carry
+// pass, then packed into a 192-bit two's-complement integer.
 template <int N>
 __device__ __forceinline__ I192 reconstruct(const int (&Ck)[N]) {
-  int acc[N], d[N];
+  constexpr int NL = kT.nlM[N];
+  int W[(N + 3) / 4], d[N];
+  digits<N, 0>(Ck, W, d);
+  int L[NL];
 #pragma unroll
-  for (int q = 0; q < N; ++q) acc[q] = 0;
-  digits<N, 0>(Ck, acc, d);
-  const uint64_t ext = d[N - 1] < 0 ? ~0ull : 0ull;
-  I192 x{(uint64_t)(int64_t)d[N - 1], ext, ext};
+  for (int l = 0; l < NL; ++l) L[l] = 0;
 #pragma unroll
-  for (int k = N - 2; k >= 0; --k) mul_add(x, (uint64_t)kT.m[k], d[k]);
-  return x;
+  for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int l = 0; l < kT.nl[k]; ++l) L[l] += __mul24(d[k], kT.P[k][l]);
+  }
+#pragma unroll
+  for (int l = 0; l + 1 < NL; ++l) {
+    L[l + 1] += L[l] >> 16;
+    L[l] &= 0xffff;
+  }
+  uint64_t w[3] = {0ull, 0ull, 0ull};
+#pragma unroll
+  for (int l = 0; l + 1 < NL; ++l) w[l >> 2] |= (uint64_t)(uint32_t)L[l] << (16 * (l & 3));
+  constexpr int lt = NL - 1;
+  const int64_t top = (int64_t)L[lt];
+  w[lt >> 2] |= (uint64_t)top << (16 * (lt & 3));
+#pragma unroll
+  for (int q = (lt >> 2) + 1; q < 3; ++q) w[q] = top < 0 ? ~0ull : 0ull;
+  return I192{w[0], w[1], w[2]};
 }
 
 // One output entry (i, j): rebuild the exact integer(s) from the N INT32
@@ -326,9 +392,9 @@ __device__ __forceinline__ I192 reconstruct(const int (&Ck)[N]) {
 // C writes).
 template <bool CPLX, int N>
 __global__ void __launch_bounds__(256) k_crt(CrtArgs a) {
-  const int64_t nbi = (a.m + 255) >> 8;
-  const int64_t j = (int64_t)blockIdx.x / nbi;
-  const int64_t i = ((int64_t)blockIdx.x % nbi) * 256 + threadIdx.x;
+  const uint32_t nbi = (uint32_t)((a.m + 255) >> 8);
+  const int64_t j = blockIdx.x / nbi;
+  const int64_t i = (int64_t)(blockIdx.x % nbi) * 256 + threadIdx.x;
   if (i >= a.m) return;
   const int ca = a.codeA[i], cb = a.codeB[j];
   const bool bad = code_bad(ca) || code_bad(cb);
@@ -442,9 +508,9 @@ hipError_t crt_n(int n, const CrtArgs &a, dim3 grid, hipStream_t st) {
 
 hipError_t launch_residues(const View &v, bool cplx, bool side_b, const int *code, int n, int beta,
                            int8_t *out, int64_t ldx, int64_t plane, hipStream_t st) {
-  const int64_t rows = (cplx && side_b) ? 2 * v.R : v.R;
-  if (rows <= 0 || ldx <= 0 || ldx % 64 != 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)(ldx / 64));
+  if (v.R <= 0 || ldx <= 0 || ldx % crt::kResEntries != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((v.R + crt::kResRows - 1) / crt::kResRows),
+                  (unsigned)(ldx / crt::kResEntries));
   if (cplx)
     return side_b ? residues_n<true, true>(v, code, n, beta, out, ldx, plane, grid, st)
                   : residues_n<true, false>(v, code, n, beta, out, ldx, plane, grid, st);

@@ -423,7 +423,7 @@ int blas_handle(int dev, rocblas_handle *h) {
 }
 
 // Workspace of one Ozaki-II product: exponent codes, the residue planes of A'
-// (N x m rows) and B' (N x n' rows), K' padded to 64 bytes per row, and the N
+// (N x m rows) and B' (N x n' rows), K' padded to 128 bytes per row, and the N
 // INT32 product planes (m x n').
 struct Plan2 {
   int N, beta;
@@ -447,7 +447,7 @@ int make_plan2(bool cplx, int64_t m, int64_t n, int64_t k, int N, Plan2 *p) {
   if (p->kprime > OZAKI2_K_MAX) return -5;
   p->beta = crt_beta(N, std::max<int64_t>(p->kprime, 1));
   if (p->beta < 1) return -14;
-  p->kpad = round_up(std::max<int64_t>(p->kprime, 1), 64);
+  p->kpad = round_up(std::max<int64_t>(p->kprime, 1), 128);
   if (m > 0x7fffffffll) return -3;
   if (p->nprime > 0x7fffffffll) return -4;
   size_t off = 0;

@@ -182,7 +182,7 @@ int crt_log2_floor(int n);
 // means too few moduli for the contraction length.
 int crt_beta(int n, int64_t kprime);
 // Residues of X' (rows of op(A), or of B' for side_b) into n planes of
-// `plane` bytes, row-major with ldx bytes per row (ldx a multiple of 64, the
+// `plane` bytes, row-major with ldx bytes per row (ldx a multiple of 128, the
 // contraction entries K' <= l < ldx written as zero).
 hipError_t launch_residues(const View &v, bool cplx, bool side_b, const int *code, int n, int beta,
                            int8_t *out, int64_t ldx, int64_t plane, hipStream_t st);
