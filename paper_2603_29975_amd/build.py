@@ -18,6 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libozaki.so")
+BLAS_SRC = os.path.join(CSRC, "blas", "ozaki_blas.cpp")
+BLAS_LIB = os.path.join(HERE, "libozaki_blas.so")  # Fortran DGEMM/ZGEMM interposer
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -62,8 +64,21 @@ def build(verbose: bool = False, extra=()) -> str:
            f"-L{ROCM_LIB}", "-lrocblas"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # host-only interposer, linked against libozaki.so next to it
+    bobj = os.path.join(BUILD, "ozaki_blas.cpp.o")
+    cmd = [HIPCC, "-O2", "-fPIC", "-std=c++17", "-Wall", "-I", os.path.join(ROOT, "include"),
+           "-c", BLAS_SRC, "-o", bobj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {BLAS_SRC}:\n{res.stdout}\n{res.stderr}")
+    tmp = BLAS_LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, bobj, f"-L{HERE}", "-lozaki",
+           "-Wl,-rpath,$ORIGIN"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, BLAS_LIB)
     if verbose:
         print(LIB)
+        print(BLAS_LIB)
     return LIB
 
 
