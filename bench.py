@@ -73,10 +73,10 @@ def source_hash(paths) -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(tune_id: int):
+def read_traffic(tune_id: int, slices: int, split: str):
     """HBM bytes per launch of the fused GEMM kernel from the committed counter
-    summary, or None when it is missing or was taken on another kernel source
-    or tuning id."""
+    summary, or None when it is missing or was taken on another kernel source,
+    tuning id, slice count or slice kind."""
     try:
         vals = {}
         with open(TRAFFIC_SUMMARY) as fh:
@@ -87,6 +87,8 @@ def read_traffic(tune_id: int):
         if vals.get("kernel_source_sha256_16") != source_hash(GEMM_SOURCES):
             return None
         if int(vals.get("tune_id", "0")) != tune_id:
+            return None
+        if int(vals.get("slices", "0")) != slices or vals.get("split", "t7") != split:
             return None
         return float(vals["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -99,6 +101,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--split", choices=["t7", "b8"], default="t7",
+                    help="Ozaki-I slice kind: trunc-7 (default) or 8-bit balanced slices")
     ap.add_argument("--moduli", type=int, default=None,
                     help="run the Ozaki-II (CRT) path with this many moduli instead of Ozaki-I")
     ap.add_argument("--workload", default="kkr2048",
@@ -150,6 +154,8 @@ def main():
     n = B.shape[1]
     ozaki2 = args.moduli is not None
     s = args.moduli if ozaki2 else args.slices
+    if oz.ozaki_set_split(args.split) != 0:
+        raise SystemExit(f"unknown split {args.split}")
     cplx = kind == "z"
     tdt = torch.complex128 if cplx else torch.float64
     log(f"workload {wl['name']} m={m} n={n} k={k} " + (f"moduli={s}" if ozaki2 else f"s={s}"))
@@ -210,7 +216,7 @@ def main():
     else:
         kernel = ("fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
                   f"{tuning['tune_id']})")
-        traffic = read_traffic(tuning["tune_id"])
+        traffic = read_traffic(tuning["tune_id"], s, args.split)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
                 "traffic": traffic, "kernel": kernel,
@@ -271,7 +277,8 @@ def main():
     cpu = None
     accuracy = None
     if not args.no_cpu_baseline:
-        cpu, accuracy = cpu_leg(wl, s, Cd, m, n, k, run_ozaki, args.cpu_seconds, ozaki2)
+        cpu, accuracy = cpu_leg(wl, s, Cd, m, n, k, run_ozaki, args.cpu_seconds, ozaki2,
+                                args.split == "b8")
 
     out = {
         "metric": METRIC,
@@ -289,6 +296,7 @@ def main():
         "config": {"workload": wl["name"], "m": m, "n": n, "k": k,
                    "operands": "complex128" if cplx else "float64",
                    "method": "ozaki2" if ozaki2 else "ozaki1",
+                   **({} if ozaki2 else {"split": args.split}),
                    ("moduli" if ozaki2 else "slices"): s,
                    ("int8_products" if ozaki2 else "pairs"): pairs,
                    "seed": wl["seed"], "inputs": wl["desc"]},
@@ -451,7 +459,7 @@ def run_selector(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False):
+def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False, b8=False):
     """The oracle timed on a bounded sample (rows 0..ms-1 of op(A) against the
     whole op(B)), plus the accuracy check of the GPU result on sampled entries
     against the oracle's double-double reference. `s` is the slice count, or
@@ -460,7 +468,8 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False):
     import torch
     from oracle import dd, metrics, ozaki
     from oracle import ozaki2 as ozaki2_model
-    model = ozaki2_model.ozaki2_gemm if ozaki2 else ozaki.ozaki_gemm
+    from oracle import ozaki_b8
+    model = ozaki2_model.ozaki2_gemm if ozaki2 else (ozaki_b8.ozaki_gemm_b8 if b8 else ozaki.ozaki_gemm)
     threads = blas_threads()
     A, B = wl["A"], wl["B"]
     torch.cuda.synchronize()
@@ -518,7 +527,7 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False):
 
     def timed(rows):
         t0 = time.perf_counter()
-        ozaki.ozaki_gemm("N", "N", A[:rows], B, s)
+        model("N", "N", A[:rows], B, s)
         return time.perf_counter() - t0
 
     # cost model t(rows) = fixed + per_row * rows from two small probes
@@ -536,8 +545,9 @@ def cpu_leg(wl, s, Cd, m, n, k, run_ozaki, target_s, ozaki2=False):
     flops = (8.0 if np.iscomplexobj(A) else 2.0) * rows * n * k
     cpu = {"value": round(flops / t / 1e12, 6), "unit": "TFLOP/s", "cores": int(threads),
            "kind": "oracle",
-           "sample": f"oracle Ozaki model (numpy + host BLAS on integer slices) for rows 0..{rows - 1} "
-                     f"of op(A) against all of op(B): {rows}x{n}x{k}, s={s}, {t:.2f} s",
+           "sample": f"oracle Ozaki model{' (8-bit balanced slices)' if b8 else ''} (numpy + host BLAS "
+                     f"on integer slices) for rows 0..{rows - 1} of op(A) against all of op(B): "
+                     f"{rows}x{n}x{k}, s={s}, {t:.2f} s",
            "host_cpus": os.cpu_count()}
     log(f"cpu oracle: {cpu}")
     return cpu, accuracy

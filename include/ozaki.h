@@ -90,6 +90,32 @@ int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                 ozaki_z beta, ozaki_z *C, int64_t ldc, int slices);
 
 /*
+ * Slice kind of ozaki_dgemm / ozaki_zgemm (and of ozaki_workspace_bytes and
+ * the debug hooks). Section 3.2 labels the Ozaki-I modes by 8s - 1 mantissa
+ * bits, i.e. slices that use all 8 bits of an INT8; the default trunc-7
+ * slices above keep 7. OZAKI_SPLIT_BAL8 selects 8-bit balanced slices:
+ *   integer    X = trunc(a * 2^(8s - 2 - e_i)), |X| < 2^(8s - 2), s <= 8.
+ *   digits     the balanced base-256 digits of X, each in [-128, 127]
+ *              (d = ((X + 128) mod 256) - 128, X <- (X - d) / 256, least
+ *              significant first); slice p holds the digit of 256^(s - p).
+ *   products   the triangle p + q <= s + 1, as above; complex data splits the
+ *              -Im b operand as it stands (its digits are not always the
+ *              negated digits of Im b).
+ *   recombine  acc = RN(acc + S_t * 2^(4 - 8t)) for t = 2..s+1, then
+ *              P = acc * 2^(e_i + f_j); alpha/beta and non-finite as above.
+ * 8s - 2 bits at s slices (trunc-7: 7s). With OZAKI_SPLIT_BAL8 the slice count
+ * argument accepts 1..OZAKI_S8_MAX. The batched entry point always uses trunc-7
+ * slices (its automatic mode raises s by adding diagonals, which needs the
+ * prefix property of trunc-7 digits). The environment variable OZAKI_SPLIT=b8
+ * sets the initial mode. ozaki_set_split returns -1 for an unknown mode.
+ */
+#define OZAKI_SPLIT_TRUNC7 0
+#define OZAKI_SPLIT_BAL8 1
+#define OZAKI_S8_MAX 8
+int ozaki_set_split(int mode);
+int ozaki_get_split(void);
+
+/*
  * Ozaki-II emulation (Section 2.2: the inputs become integer matrices, their
  * products are taken modulo several pairwise-coprime moduli on the INT8
  * matrix cores and the Chinese remainder theorem rebuilds the result;

@@ -30,12 +30,15 @@ __all__ = [
     "ozaki_load_selector", "ozaki_autotune", "ozaki_tune_set", "ozaki_tune_get",
     "ozaki_tune_configs", "ozaki_tune_save", "ozaki_tune_load", "ozaki_tune_clear",
     "ozaki2_dgemm", "ozaki2_zgemm", "ozaki2_moduli", "ozaki2_beta_bits", "ozaki2_workspace_bytes",
-    "MODULI_MIN", "MODULI_MAX", "K2_MAX",
+    "MODULI_MIN", "MODULI_MAX", "K2_MAX", "ozaki_set_split", "ozaki_get_split", "SPLIT_TRUNC7",
+    "SPLIT_BAL8", "S8_MAX",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libozaki.so")
 S_MAX = 12
+SPLIT_TRUNC7, SPLIT_BAL8 = 0, 1  # Ozaki-I slice kinds (ozaki_set_split)
+S8_MAX = 8                       # slices accepted with 8-bit balanced slices
 MODULI_MIN, MODULI_MAX = 2, 20   # Ozaki-II moduli counts
 K2_MAX = 131072                  # Ozaki-II contraction length K' (k, or 2k complex)
 
@@ -67,6 +70,8 @@ _SIG = {
     "ozaki2_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
                                 _i64, ozaki_z, _vp, _i64, _c.c_int]),
     "ozaki2_moduli": (_c.c_int, [_c.c_int, _vp]),
+    "ozaki_set_split": (_c.c_int, [_c.c_int]),
+    "ozaki_get_split": (_c.c_int, []),
     "ozaki2_beta_bits": (_c.c_int, [_c.c_int, _i64]),
     "ozaki2_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
     "ozaki_native_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp,
@@ -176,6 +181,18 @@ def ozaki2_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, m
     _bind_stream()
     return library().ozaki2_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
                                   _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(moduli))
+
+
+def ozaki_set_split(mode) -> int:
+    """Slice kind of ozaki_dgemm/ozaki_zgemm: SPLIT_TRUNC7 (default) or SPLIT_BAL8
+    (8-bit balanced slices, 1..S8_MAX slices); "t7"/"b8" are accepted too."""
+    if isinstance(mode, str):
+        mode = {"t7": SPLIT_TRUNC7, "b8": SPLIT_BAL8}.get(mode, -1)
+    return library().ozaki_set_split(int(mode))
+
+
+def ozaki_get_split() -> int:
+    return library().ozaki_get_split()
 
 
 def ozaki2_moduli(moduli):

@@ -39,6 +39,7 @@ struct DevInfo {
 
 struct State {
   hipStream_t stream = nullptr;
+  int split = -1;  // OZAKI_SPLIT_* of the single-product calls (-1: not read from OZAKI_SPLIT yet)
   void *user_ws = nullptr;
   size_t user_ws_bytes = 0;
   void *own_ws[kMaxDev] = {};
@@ -47,6 +48,19 @@ struct State {
 };
 
 State g;
+
+// Slice kind of ozaki_dgemm / ozaki_zgemm and the debug hooks: set by
+// ozaki_set_split, else OZAKI_SPLIT=b8 in the environment, else trunc-7.
+bool split_b8() {
+  if (g.split < 0) {
+    const char *e = getenv("OZAKI_SPLIT");
+    g.split = (e != nullptr && (std::strcmp(e, "b8") == 0 || std::strcmp(e, "1") == 0))
+                  ? OZAKI_SPLIT_BAL8
+                  : OZAKI_SPLIT_TRUNC7;
+  }
+  return g.split == OZAKI_SPLIT_BAL8;
+}
+int max_slices(bool b8) { return b8 ? kS8Max : OZAKI_S_MAX; }
 
 // ---------------------------------------------------------------- timing
 struct Mark {
@@ -151,6 +165,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct Plan {
   int S;
   bool cplx;
+  bool b8;                    // 8-bit balanced slices instead of trunc-7
   int64_t m, n, k;
   int64_t kprime, kpad, nkb;
   int64_t nprime;             // rows of B' (n or 2n)
@@ -159,10 +174,11 @@ struct Plan {
   int64_t kb_chunk;
 };
 
-Plan make_plan(bool cplx, int64_t m, int64_t n, int64_t k, int S, int num_cu) {
+Plan make_plan(bool cplx, int64_t m, int64_t n, int64_t k, int S, int num_cu, bool b8 = false) {
   Plan p{};
   p.S = S;
   p.cplx = cplx;
+  p.b8 = b8;
   p.m = m;
   p.n = n;
   p.k = k;
@@ -172,7 +188,7 @@ Plan make_plan(bool cplx, int64_t m, int64_t n, int64_t k, int S, int num_cu) {
   p.nprime = cplx ? 2 * n : n;
   p.nrbQ = round_up(std::max<int64_t>(m, 1), kRowPad) / 32;
   p.nrbP = round_up(std::max<int64_t>(p.nprime, 1), kRowPad) / 32;
-  p.kb_chunk = kb_chunk_for(S);
+  p.kb_chunk = kb_chunk_for(S, b8);
   size_t off = 0;
   p.off_codeA = off;
   off += align256(sizeof(int) * (size_t)std::max<int64_t>(m, 1));
@@ -297,8 +313,10 @@ int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t
   if ((rc = hip_rc(launch_scan(vb, p.cplx, codeB, st)))) return rc;
   phase_end(mk, st);
   mk = phase_begin(OZAKI_PHASE_SPLIT, st);
-  if ((rc = hip_rc(launch_split(va, p.cplx, false, codeA, p.S, SA, p.nrbQ, p.nkb, st)))) return rc;
-  if ((rc = hip_rc(launch_split(vb, p.cplx, true, codeB, p.S, SB, p.nrbP, p.nkb, st)))) return rc;
+  if ((rc = hip_rc(launch_split(va, p.cplx, false, codeA, p.S, SA, p.nrbQ, p.nkb, st, p.b8))))
+    return rc;
+  if ((rc = hip_rc(launch_split(vb, p.cplx, true, codeB, p.S, SB, p.nrbP, p.nkb, st, p.b8))))
+    return rc;
   phase_end(mk, st);
   return OZAKI_OK;
 }
@@ -321,6 +339,8 @@ GemmProblem gemm_problem(const Plan &p, char *ws, double ar, double ai, double b
   a.bi = bi;
   a.beta_zero = beta_zero ? 1 : 0;
   a.cplx = p.cplx ? 1 : 0;
+  a.wbits = p.b8 ? 8 : kDigitBits;
+  a.woff = p.b8 ? 4 : 0;
   a.C = C;
   a.ldc = ldc;
   a.raw = raw;
@@ -342,7 +362,8 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
                   double br, double bi, void *C, int64_t ldc, int slices) {
   int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
   if (rc) return rc;
-  if (slices < 1 || slices > OZAKI_S_MAX) return -14;
+  const bool b8 = split_b8();
+  if (slices < 1 || slices > max_slices(b8)) return -14;
   if (m == 0 || n == 0) return OZAKI_OK;
   if (C == nullptr) return -12;
   const bool alpha_zero = ar == 0.0 && ai == 0.0;
@@ -356,7 +377,7 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
   if (B == nullptr) return -9;
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu);
+  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu, b8);
   void *wsv = nullptr;
   if ((rc = get_workspace(p.total, &wsv))) return rc;
   char *ws = static_cast<char *>(wsv);
@@ -1704,14 +1725,23 @@ int ozaki_set_workspace(void *device_ptr, size_t bytes) {
 
 size_t ozaki_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int slices) {
   kind = up(kind);
+  const bool b8 = split_b8();
   if ((kind != 'D' && kind != 'Z') || m < 0 || n < 0 || k < 0 || slices < 1 ||
-      slices > OZAKI_S_MAX)
+      slices > max_slices(b8))
     return 0;
   int dev = 0;
   int num_cu = 256;
   if (current_device(&dev) == OZAKI_OK) num_cu = g.dev[dev].num_cu;
-  return make_plan(kind == 'Z', m, n, k, slices, num_cu).total;
+  return make_plan(kind == 'Z', m, n, k, slices, num_cu, b8).total;
 }
+
+int ozaki_set_split(int mode) {
+  if (mode != OZAKI_SPLIT_TRUNC7 && mode != OZAKI_SPLIT_BAL8) return -1;
+  g.split = mode;
+  return OZAKI_OK;
+}
+
+int ozaki_get_split(void) { return split_b8() ? OZAKI_SPLIT_BAL8 : OZAKI_SPLIT_TRUNC7; }
 
 int ozaki_timing_enable(int on) {
   g_tm.on = on != 0;
@@ -1807,7 +1837,8 @@ int ozaki_debug_split(char kind, char side, char trans, int64_t rows, int64_t L,
   bool cplx = false;
   int rc = debug_view(kind, side, trans, rows, L, X, ldx, &v, &cplx);
   if (rc) return rc;
-  if (slices < 1 || slices > OZAKI_S_MAX) return -8;
+  const bool b8 = split_b8();
+  if (slices < 1 || slices > max_slices(b8)) return -8;
   if (rows == 0 || L == 0) return OZAKI_OK;
   if (digits == nullptr) return -9;
   const bool side_b = up(side) == 'B';
@@ -1822,7 +1853,8 @@ int ozaki_debug_split(char kind, char side, char trans, int64_t rows, int64_t L,
   int8_t *packed = static_cast<int8_t *>(wsv) + code_bytes;
   if ((rc = hip_rc(launch_fill_i32(code, rows, 0, g.stream)))) return rc;
   if ((rc = hip_rc(launch_scan(v, cplx, code, g.stream)))) return rc;
-  if ((rc = hip_rc(launch_split(v, cplx, side_b, code, slices, packed, nrb, kpad / 32, g.stream))))
+  if ((rc = hip_rc(launch_split(v, cplx, side_b, code, slices, packed, nrb, kpad / 32, g.stream,
+                                b8))))
     return rc;
   return hip_rc(launch_unpack(packed, cplx, side_b, rows, L, slices, nrb, kpad / 32, digits, g.stream));
 }
@@ -1835,14 +1867,15 @@ int ozaki_debug_diagonals(char kind, char transa, char transb, int64_t m, int64_
   const bool cplx = kind == 'Z';
   int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, std::max<int64_t>(1, m));
   if (rc) return rc;
-  if (slices < 1 || slices > OZAKI_S_MAX) return -14;
+  const bool b8 = split_b8();
+  if (slices < 1 || slices > max_slices(b8)) return -14;
   if (m == 0 || n == 0 || k == 0) return OZAKI_OK;
   if (S == nullptr) return -15;
   if (A == nullptr) return -7;
   if (B == nullptr) return -9;
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu);
+  const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu, b8);
   void *wsv = nullptr;
   if ((rc = get_workspace(p.total, &wsv))) return rc;
   char *ws = static_cast<char *>(wsv);

@@ -307,7 +307,7 @@ constexpr int waves_of() {
 
 }  // namespace
 
-int64_t kb_chunk_for(int S) { return chunk_blocks(S); }
+int64_t kb_chunk_for(int S, bool b8) { return chunk_blocks(S, b8 ? 128 : 127); }
 
 int gemm_num_configs() { return 2 * kNumCfg; }
 

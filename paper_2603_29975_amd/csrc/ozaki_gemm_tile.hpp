@@ -42,9 +42,10 @@ __device__ __forceinline__ void copy_frag(const int8_t *src_lane, const int8_t *
 }
 #pragma clang diagnostic pop
 
-// Contraction blocks of 32 a chunk may hold: S * 32 * kb * 127^2 <= 2^31 - 1.
-__host__ __device__ constexpr int64_t chunk_blocks(int S) {
-  return (int64_t)(2147483647ll / ((int64_t)S * 32 * 127 * 127));
+// Contraction blocks of 32 a chunk may hold: S * 32 * kb * dmax^2 <= 2^31 - 1
+// with dmax = 127 (trunc-7 digits) or 128 (8-bit balanced digits).
+__host__ __device__ constexpr int64_t chunk_blocks(int S, int dmax = 127) {
+  return (int64_t)(2147483647ll / ((int64_t)S * 32 * dmax * dmax));
 }
 
 // Exact int64 carry of one block's S INT32 accumulator sets into its carry
@@ -70,7 +71,8 @@ __device__ __forceinline__ void carry_block(v16i (&acc)[S], int64_t *ws, int lan
 // Recombination and store of one 32 x 32 block: row i of the output, lane
 // register r at column side j' = jbase + 8 (r / 4) + r % 4. Diagonal t + 2 of
 // the block is acc[t] (or, for a chunked contraction, the int64 total in the
-// carry space `ws`). acc = RN(acc + S_t 2^-7t) for t = 2..S+1, then
+// carry space `ws`). acc = RN(acc + S_t 2^(woff - wbits t)) for t = 2..S+1
+// (2^-7t for trunc-7 slices, 2^(4-8t) for 8-bit balanced ones), then
 // ldexp(acc, e_i + f_j) and alpha/beta without fused multiply-adds; rows or
 // columns flagged non-finite give NaN. RAW writes the exact diagonals instead.
 template <int S, bool CHUNKED, bool RAW>
@@ -114,7 +116,7 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
     double acc64 = 0.0;
 #pragma unroll
     for (int t = 0; t < S; ++t)
-      acc64 = add_rn(acc64, ldexp((double)total(t, r), -kDigitBits * (t + 2)));
+      acc64 = add_rn(acc64, ldexp((double)total(t, r), a.woff - a.wbits * (t + 2)));
     val[r] = acc64;
   }
   if (!row_ok) return;

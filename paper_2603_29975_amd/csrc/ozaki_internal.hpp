@@ -16,8 +16,10 @@ hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st);
 // Slicing step: writes all nrb*32 x nkb*32 packed rows/entries of S slices.
 // side_b selects the B-operand construction for complex data (rows 2j and
 // 2j+1 hold (Re, -Im) and (Im, Re) of column j along the contraction).
+// b8 selects the 8-bit balanced slices (S <= kS8Max) instead of trunc-7.
+constexpr int kS8Max = 8;
 hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S,
-                        int8_t *out, int64_t nrb, int64_t nkb, hipStream_t st);
+                        int8_t *out, int64_t nrb, int64_t nkb, hipStream_t st, bool b8 = false);
 
 // Batched scan and split: task tables in device memory. A scan task covers
 // all rows of one operand view over its whole contraction (codes are stored,
@@ -66,6 +68,7 @@ struct GemmProblem {
   double ar, ai, br, bi;
   int beta_zero;
   int cplx;
+  int wbits, woff;  // diagonal t (2..S+1) carries weight 2^(woff - wbits t): 7, 0 or 8, 4
   void *C;
   int64_t ldc;
   int64_t *raw;  // raw diagonal output (debug) or nullptr
@@ -92,8 +95,8 @@ int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime);
 hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, hipStream_t st);
 
 // Contraction blocks (of 32) that one INT32 accumulation may cover for S
-// slices: S * 32 * kb * 127^2 < 2^31.
-int64_t kb_chunk_for(int S);
+// slices: S * 32 * kb * 127^2 < 2^31 (8-bit slices: 128^2).
+int64_t kb_chunk_for(int S, bool b8 = false);
 // Tuning ids of the fused GEMM (0 .. gemm_num_configs() - 1): 2 * tile
 // configuration + tile order.
 int gemm_num_configs();

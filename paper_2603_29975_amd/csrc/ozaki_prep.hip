@@ -118,6 +118,15 @@ __device__ __forceinline__ uint64_t top_bits(const Sig &x) {
   return (sh > -64) ? (x.m >> (-sh)) : 0ull;
 }
 
+// trunc(|x| 2^NB) for NB <= 62 (|x| < 1 after the exponent shift, so the
+// result stays below 2^NB).
+template <int NB>
+__device__ __forceinline__ uint64_t top_nbits(const Sig &x) {
+  const int sh = x.sh0 + NB;
+  if (sh >= 0) return x.m << sh;
+  return (sh > -64) ? (x.m >> (-sh)) : 0ull;
+}
+
 // View rows and contraction entries (elements) covered by one split block.
 template <bool CPLX, bool SIDEB>
 struct SplitTile {
@@ -153,7 +162,7 @@ __device__ __forceinline__ void load_split_tile(const View &v, int64_t bx, int64
   __syncthreads();
 }
 
-template <bool CPLX, bool SIDEB, int SC, bool TRP>
+template <bool CPLX, bool SIDEB, int SC, bool TRP, bool B8>
 __device__ __forceinline__ void split_block(const View &v, const int *code, int S, int8_t *out,
                                             int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
                                             const double *tile) {
@@ -218,7 +227,38 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
     }
   }
 
-  if constexpr (SC > 0) {
+  if constexpr (B8) {
+    // 8-bit balanced slices: X = trunc(x 2^(8S - 2)) with the sign of x, then
+    // its balanced base-256 digits d in [-128, 127] from the least significant
+    // one up (d = ((X + 128) mod 256) - 128, X <- (X - d) / 256); slice p holds
+    // the digit of weight 256^(S - p). Every value is split as it stands, so
+    // the -Im row of complex B gets the digits of -Im.
+    static_assert(SC >= 1 && SC <= 8, "8-bit slices need 8S - 2 <= 62");
+    int64_t X[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const int64_t u = (int64_t)top_nbits<8 * SC - 2>(sg[x]);
+      X[x] = sg[x].neg ? -u : u;
+    }
+#pragma unroll
+    for (int p = SC; p >= 1; --p) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          int64_t &xv = X[4 * q + b];
+          const int d = (int)((xv + 128) & 255) - 128;
+          xv = (xv - d) >> 8;
+          word |= ((uint32_t)d & 0xffu) << (8 * b);
+        }
+        w[q] = word;
+      }
+      int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
+      *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  } else if constexpr (SC > 0) {
     // S known at compile time and 7S <= 63: one integer per value, digits by
     // constant shifts, signs applied four bytes at a time.
     uint64_t T[16];
@@ -263,17 +303,29 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
   }
 }
 
-template <bool CPLX, bool SIDEB, bool TRP>
+template <bool CPLX, bool SIDEB, bool TRP, bool B8>
 __device__ __forceinline__ void split_s(const View &v, const int *code, int S, int8_t *out,
                                         int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
                                         const double *tile) {
-  switch (S) {
+  if constexpr (B8) {
+    // 1..8 slices (the host rejects more)
+    switch (S) {
 #define OZ_SPLIT(N) \
-  case N: split_block<CPLX, SIDEB, N, TRP>(v, code, S, out, nrb, nkb, bx, by, tile); break;
-    OZ_SPLIT(1) OZ_SPLIT(2) OZ_SPLIT(3) OZ_SPLIT(4) OZ_SPLIT(5) OZ_SPLIT(6) OZ_SPLIT(7)
-    OZ_SPLIT(8) OZ_SPLIT(9)
+  case N: split_block<CPLX, SIDEB, N, TRP, true>(v, code, S, out, nrb, nkb, bx, by, tile); break;
+      OZ_SPLIT(1) OZ_SPLIT(2) OZ_SPLIT(3) OZ_SPLIT(4) OZ_SPLIT(5) OZ_SPLIT(6) OZ_SPLIT(7)
+      OZ_SPLIT(8)
 #undef OZ_SPLIT
-    default: split_block<CPLX, SIDEB, 0, TRP>(v, code, S, out, nrb, nkb, bx, by, tile); break;
+      default: break;
+    }
+  } else {
+    switch (S) {
+#define OZ_SPLIT(N) \
+  case N: split_block<CPLX, SIDEB, N, TRP, false>(v, code, S, out, nrb, nkb, bx, by, tile); break;
+      OZ_SPLIT(1) OZ_SPLIT(2) OZ_SPLIT(3) OZ_SPLIT(4) OZ_SPLIT(5) OZ_SPLIT(6) OZ_SPLIT(7)
+      OZ_SPLIT(8) OZ_SPLIT(9)
+#undef OZ_SPLIT
+      default: split_block<CPLX, SIDEB, 0, TRP, false>(v, code, S, out, nrb, nkb, bx, by, tile); break;
+    }
   }
 }
 
@@ -284,26 +336,26 @@ __host__ __device__ __forceinline__ bool split_staged(const View &v) {
   return v.sl == 1 && v.sr != 1;
 }
 
-template <bool CPLX, bool SIDEB>
+template <bool CPLX, bool SIDEB, bool B8 = false>
 __device__ __forceinline__ void split_dispatch(const View &v, const int *code, int S, int8_t *out,
                                                int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
                                                double *tile) {
   if (tile != nullptr && split_staged(v)) {
     load_split_tile<CPLX, SIDEB>(v, bx, by, tile);
-    split_s<CPLX, SIDEB, true>(v, code, S, out, nrb, nkb, bx, by, tile);
+    split_s<CPLX, SIDEB, true, B8>(v, code, S, out, nrb, nkb, bx, by, tile);
   } else {
-    split_s<CPLX, SIDEB, false>(v, code, S, out, nrb, nkb, bx, by, nullptr);
+    split_s<CPLX, SIDEB, false, B8>(v, code, S, out, nrb, nkb, bx, by, nullptr);
   }
 }
 
-template <bool CPLX, bool SIDEB, bool STAGED>
+template <bool CPLX, bool SIDEB, bool STAGED, bool B8>
 __global__ void __launch_bounds__(256) k_split(View v, const int *code, int S, int8_t *out,
                                                int64_t nrb, int64_t nkb) {
   if constexpr (STAGED) {
     __shared__ __attribute__((aligned(16))) double tile[kSplitTileDoubles];
-    split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, tile);
+    split_dispatch<CPLX, SIDEB, B8>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, tile);
   } else {
-    split_dispatch<CPLX, SIDEB>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, nullptr);
+    split_dispatch<CPLX, SIDEB, B8>(v, code, S, out, nrb, nkb, blockIdx.x, blockIdx.y, nullptr);
   }
 }
 
@@ -382,8 +434,9 @@ __global__ void __launch_bounds__(256) k_unpack(const int8_t *packed, int64_t R,
   } else if (!SIDEB) {
     val = packed[frag_offset(p, r, 2 * l + part, nrb, nkb)];
   } else {
-    val = part == 0 ? packed[frag_offset(p, 2 * r, 2 * l, nrb, nkb)]
-                    : -packed[frag_offset(p, 2 * r, 2 * l + 1, nrb, nkb)];
+    // row 2j holds (Re, -Im), row 2j+1 (Im, Re): the Re and Im digits are the
+    // even entries of the two rows
+    val = packed[frag_offset(p, 2 * r + part, 2 * l, nrb, nkb)];
   }
   digits[idx] = (int8_t)val;
 }
@@ -462,13 +515,12 @@ hipError_t launch_scan(const View &v, bool cplx, int *code, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S, int8_t *out,
-                        int64_t nrb, int64_t nkb, hipStream_t st) {
-  // nrb * 32 is a multiple of 64 (rows padded to 128) and nkb * 32 a multiple
-  // of 64 (contraction padded to 64): the grid covers the buffer exactly.
-  dim3 g((unsigned)(nrb * 32 / 64), (unsigned)(nkb * 32 / 64));
+namespace {
+template <bool B8>
+void split_launch(const View &v, bool cplx, bool side_b, const int *code, int S, int8_t *out,
+                  int64_t nrb, int64_t nkb, dim3 g, hipStream_t st) {
 #define OZ_SPLIT_LAUNCH(C, B, T) \
-  hipLaunchKernelGGL((k_split<C, B, T>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb)
+  hipLaunchKernelGGL((k_split<C, B, T, B8>), g, dim3(256), 0, st, v, code, S, out, nrb, nkb)
   const bool staged = split_staged(v);
   if (cplx && side_b) {
     if (staged) OZ_SPLIT_LAUNCH(true, true, true); else OZ_SPLIT_LAUNCH(true, true, false);
@@ -478,6 +530,19 @@ hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, 
     if (staged) OZ_SPLIT_LAUNCH(false, false, true); else OZ_SPLIT_LAUNCH(false, false, false);
   }
 #undef OZ_SPLIT_LAUNCH
+}
+}  // namespace
+
+hipError_t launch_split(const View &v, bool cplx, bool side_b, const int *code, int S, int8_t *out,
+                        int64_t nrb, int64_t nkb, hipStream_t st, bool b8) {
+  // nrb * 32 is a multiple of 64 (rows padded to 128) and nkb * 32 a multiple
+  // of 64 (contraction padded to 64): the grid covers the buffer exactly.
+  if (b8 && (S < 1 || S > kS8Max)) return hipErrorInvalidValue;
+  dim3 g((unsigned)(nrb * 32 / 64), (unsigned)(nkb * 32 / 64));
+  if (b8)
+    split_launch<true>(v, cplx, side_b, code, S, out, nrb, nkb, g, st);
+  else
+    split_launch<false>(v, cplx, side_b, code, S, out, nrb, nkb, g, st);
   return hipGetLastError();
 }
 
