@@ -3,8 +3,9 @@
 
 Workload (default): complex128 C = A B with M = N = K = 2048 shaped like the
 KKR multiple-scattering matrix (A = I - T G with 64 diagonal blocks of 32,
-seed 1002) and a complex Gaussian B, at s = 7 slices, the smallest slice count
-whose componentwise error reaches 1e-12 on this input. One step is one whole
+seed 1002) and a complex Gaussian B, with 8-bit balanced slices at s = 6, the
+smallest slice count whose componentwise error reaches 1e-12 on this input
+(the 7-bit slices need s = 7: --split t7 --slices 7). One step is one whole
 ozaki_zgemm call (exponent scan, slicing, fused slice GEMM + recombination) on
 operands already resident in HBM.
 
@@ -33,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 GEMM_SOURCES = [os.path.join(ROOT, "paper_2603_29975_amd", "csrc", f)
                 for f in ("ozaki_gemm.hip", "ozaki_gemm_tile.hpp")]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ozgemm_kkr2048_s7_traffic.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ozgemm_kkr2048_{split}_s{slices}_traffic.txt")
 TUNE_CACHE = os.path.join(ROOT, "paper_2603_29975_amd", "tune_gfx950.json")
 
 
@@ -79,7 +80,7 @@ def read_traffic(tune_id: int, slices: int, split: str):
     tuning id, slice count or slice kind."""
     try:
         vals = {}
-        with open(TRAFFIC_SUMMARY) as fh:
+        with open(TRAFFIC_SUMMARY.format(split=split, slices=slices)) as fh:
             for line in fh:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.split("=", 1)
@@ -100,9 +101,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--slices", type=int, default=7)
-    ap.add_argument("--split", choices=["t7", "b8"], default="t7",
-                    help="Ozaki-I slice kind: trunc-7 (default) or 8-bit balanced slices")
+    ap.add_argument("--slices", type=int, default=None,
+                    help="slice count (default: 6 with --split b8, 7 with --split t7)")
+    ap.add_argument("--split", choices=["t7", "b8"], default="b8",
+                    help="Ozaki-I slice kind: 8-bit balanced (default) or trunc-7 slices")
     ap.add_argument("--moduli", type=int, default=None,
                     help="run the Ozaki-II (CRT) path with this many moduli instead of Ozaki-I")
     ap.add_argument("--workload", default="kkr2048",
@@ -142,6 +144,8 @@ def main():
     oz.library()   # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload in ("batched512", "selector512") and args.slices is None:
+        args.slices = 7          # the batched path uses 7-bit slices
     if args.workload == "batched512":
         return run_batched(args)
     if args.workload == "selector512":
@@ -153,6 +157,8 @@ def main():
     m, k = A.shape
     n = B.shape[1]
     ozaki2 = args.moduli is not None
+    if args.slices is None:
+        args.slices = 6 if args.split == "b8" else 7
     s = args.moduli if ozaki2 else args.slices
     if oz.ozaki_set_split(args.split) != 0:
         raise SystemExit(f"unknown split {args.split}")
@@ -216,7 +222,8 @@ def main():
     else:
         kernel = ("fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
                   f"{tuning['tune_id']})")
-        traffic = read_traffic(tuning["tune_id"], s, args.split)
+        traffic = (read_traffic(tuning["tune_id"], s, args.split)
+                   if args.workload == "kkr2048" else None)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
                 "traffic": traffic, "kernel": kernel,
