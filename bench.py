@@ -109,7 +109,8 @@ def main():
                     help="run the Ozaki-II (CRT) path with this many moduli instead of Ozaki-I")
     ap.add_argument("--workload", default="kkr2048",
                     choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512",
-                             "selector512"])
+                             "selector512", "kkrinv2048"])
+    ap.add_argument("--nb", type=int, default=256, help="kkrinv2048: LU panel width")
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2603_29975_amd",
                                                          "selector_weights.npz"),
                     help="trained selector weights (selector512 workload)")
@@ -146,6 +147,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload in ("batched512", "selector512") and args.slices is None:
         args.slices = 7          # the batched path uses 7-bit slices
+    if args.workload == "kkrinv2048":
+        return run_lu(args)
     if args.workload == "batched512":
         return run_batched(args)
     if args.workload == "selector512":
@@ -462,6 +465,79 @@ def run_selector(args):
                    "selector": os.path.basename(args.selector), "margin": margin,
                    "kappa": args.kappa, "seed": 1003},
         "roofline": None, "cpu_baseline": None, "selector": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_lu(args):
+    """Blocked LU + inverse of the 2048 x 2048 KKR matrix A = I - T G (seed 1002)
+    with emulated trailing updates, beside the same algorithm with the native
+    FP64 ZGEMM; reports the inverse's deviation from the native-update inverse."""
+    import numpy as np
+    import torch
+    import paper_2603_29975_amd as oz
+    from workloads import kkr_operands
+    if args.slices is None:
+        args.slices = 6 if args.split == "b8" else 7
+    s = args.slices
+    if oz.ozaki_set_split(args.split) != 0:
+        raise SystemExit(f"unknown split {args.split}")
+    A, _ = kkr_operands(64, seed=1002)
+    n = A.shape[0]
+    dev = torch.device("cuda:0")
+    A0 = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev)
+    W = torch.empty_like(A0)
+    X = torch.empty_like(A0)
+    ipiv = torch.zeros(n, dtype=torch.int64, device=dev)
+    log(f"workload kkrinv2048: n={n} nb={args.nb} split={args.split} s={s}")
+
+    def step(slices):
+        W.copy_(A0)
+        rc = oz.ozaki_zgetrf(n, W, n, ipiv, args.nb, slices)
+        if rc != 0:
+            raise RuntimeError(f"ozaki_zgetrf: {oz.ozaki_status_string(rc)}")
+        rc = oz.ozaki_zgetri(n, W, n, ipiv, X, n, args.nb, slices)
+        if rc != 0:
+            raise RuntimeError(f"ozaki_zgetri: {oz.ozaki_status_string(rc)}")
+
+    def timed(slices):
+        for _ in range(args.warmup):
+            step(slices)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(slices)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ms_nat = timed(0)
+    X_nat = X.clone()
+    ms = timed(s)
+    flops = 8.0 * n ** 3                       # complex LU (8/3 n^3) + inverse from the factors (16/3 n^3)
+    scale = X_nat.abs().max().item()
+    dev_err = (X - X_nat).abs().max().item() / scale
+    eye = torch.eye(n, dtype=A0.dtype, device=dev)
+    resid = (X.T @ A0.T - eye).abs().max().item()         # row-major views: (A^-1 A)^T
+    errs = {}
+    for sv in range(max(3, s - 2), s + 2):
+        if sv > (8 if args.split == "b8" else 12):
+            continue
+        step(sv)
+        errs[sv] = (X - X_nat).abs().max().item() / scale
+    out = {
+        "metric": "effective FP64 TFLOP/s, blocked LU + inverse of the KKR matrix (8 n^3 flops)",
+        "value": round(flops / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "kkr_lu_inverse_2048", "n": n, "nb": args.nb, "split": args.split,
+                   "slices": s, "seed": 1002},
+        "native_updates": {"ms_per_step": round(ms_nat, 4),
+                           "tflops": round(flops / (ms_nat * 1e-3) / 1e12, 3)},
+        "inverse_deviation_from_native": dev_err,
+        "inverse_deviation_by_slices": errs,
+        "residual_max_abs_XA_minus_I": resid,
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -70,7 +70,8 @@ enum ozaki_status {
   OZAKI_ERR_NO_DEVICE = 4,    /* no usable gfx950 device */
   OZAKI_ERR_INTERNAL = 5,
   OZAKI_ERR_NO_SELECTOR = 6,  /* automatic slice selection without a loaded selector */
-  OZAKI_ERR_IO = 7            /* tuning cache file missing, unwritable or malformed */
+  OZAKI_ERR_IO = 7,           /* tuning cache file missing, unwritable or malformed */
+  OZAKI_ERR_SINGULAR = 8      /* ozaki_zgetrf met an exactly zero pivot */
 };
 
 /*
@@ -158,6 +159,37 @@ int ozaki2_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
 int ozaki2_moduli(int moduli, int32_t *out);
 int ozaki2_beta_bits(int moduli, int64_t kprime);
 size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int moduli);
+
+/*
+ * Blocked LU with partial pivoting and the inverse of an n x n complex matrix,
+ * the step around the ZGEMM in the paper's solver (the multiple-scattering
+ * matrix is inverted by LU; ZGEMM and ZTRSM dominate its run time, Section
+ * 3.2). The trailing updates C -= A B are ZGEMMs through ozaki_zgemm with
+ * `slices` slices of the current slice kind, or the native FP64 ZGEMM for
+ * slices == 0. Every other step runs in its own kernels with each complex
+ * operation written out as separately rounded real operations:
+ *   product  (ar br - ai bi, ar bi + ai br)
+ *   quotient d = br^2 + bi^2, ((ar br + ai bi) / d, (ai br - ar bi) / d)
+ *   pivot    the first row of the largest |Re| + |Im| in the column
+ * ozaki_zgetrf: A (device, column-major, lda >= n) is overwritten by L (unit
+ *   lower, below the diagonal) and U, with P A = L U; ipiv (device, n int64)
+ *   receives the 0-based pivot row of each column (rows c and ipiv[c]
+ *   exchanged in order). Panels of nb columns: pivot, swap and rank-one
+ *   update per column inside the panel, the interchanges applied to the other
+ *   columns, U12 = L11^-1 A12 (forward substitution, one thread per column),
+ *   then A22 -= L21 U12. Returns OZAKI_ERR_SINGULAR (factors complete) if a
+ *   pivot is exactly zero. Synchronises with the stream before returning.
+ * ozaki_zgetri: X (device, ldx >= n, not overlapping LU) = A^-1 from the
+ *   factors: X = P I; block rows of nb top down X_i = L_ii^-1 X_i, X_below -=
+ *   L_below,i X_i; then bottom up X_i = U_ii^-1 X_i (backward substitution,
+ *   the sum in increasing column order, then the quotient), X_above -=
+ *   U_above,i X_i.
+ * Argument numbers: n 1, A/LU 2, lda 3, ipiv 4, nb 5, slices 6 (0..the slice
+ * limit of the current kind), X 7, ldx 8.
+ */
+int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, int slices);
+int ozaki_zgetri(int64_t n, const ozaki_z *LU, int64_t lda, const int64_t *ipiv, ozaki_z *X,
+                 int64_t ldx, int64_t nb, int slices);
 
 /*
  * Native FP64 GEMM on the FP64 matrix cores (the comparator the paper uses as

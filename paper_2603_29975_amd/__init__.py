@@ -31,7 +31,7 @@ __all__ = [
     "ozaki_tune_configs", "ozaki_tune_save", "ozaki_tune_load", "ozaki_tune_clear",
     "ozaki2_dgemm", "ozaki2_zgemm", "ozaki2_moduli", "ozaki2_beta_bits", "ozaki2_workspace_bytes",
     "MODULI_MIN", "MODULI_MAX", "K2_MAX", "ozaki_set_split", "ozaki_get_split", "SPLIT_TRUNC7",
-    "SPLIT_BAL8", "S8_MAX",
+    "SPLIT_BAL8", "S8_MAX", "ozaki_zgetrf", "ozaki_zgetri",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -71,6 +71,8 @@ _SIG = {
                                 _i64, ozaki_z, _vp, _i64, _c.c_int]),
     "ozaki2_moduli": (_c.c_int, [_c.c_int, _vp]),
     "ozaki_set_split": (_c.c_int, [_c.c_int]),
+    "ozaki_zgetrf": (_c.c_int, [_i64, _vp, _i64, _vp, _i64, _c.c_int]),
+    "ozaki_zgetri": (_c.c_int, [_i64, _vp, _i64, _vp, _vp, _i64, _i64, _c.c_int]),
     "ozaki_get_split": (_c.c_int, []),
     "ozaki2_beta_bits": (_c.c_int, [_c.c_int, _i64]),
     "ozaki2_workspace_bytes": (_c.c_size_t, [_c.c_char, _i64, _i64, _i64, _c.c_int]),
@@ -189,6 +191,21 @@ def ozaki_set_split(mode) -> int:
     if isinstance(mode, str):
         mode = {"t7": SPLIT_TRUNC7, "b8": SPLIT_BAL8}.get(mode, -1)
     return library().ozaki_set_split(int(mode))
+
+
+def ozaki_zgetrf(n, A, lda, ipiv, nb, slices) -> int:
+    """Blocked LU with partial pivoting in place (A: complex128 device buffer,
+    ipiv: int64 device buffer of n, 0-based); slices = 0 uses the native FP64
+    ZGEMM for the trailing updates. Synchronises before returning."""
+    _bind_stream()
+    return library().ozaki_zgetrf(int(n), _ptr(A), int(lda), _ptr(ipiv), int(nb), int(slices))
+
+
+def ozaki_zgetri(n, LU, lda, ipiv, X, ldx, nb, slices) -> int:
+    """X = A^-1 from the factors of ozaki_zgetrf (X must not overlap LU)."""
+    _bind_stream()
+    return library().ozaki_zgetri(int(n), _ptr(LU), int(lda), _ptr(ipiv), _ptr(X), int(ldx),
+                                  int(nb), int(slices))
 
 
 def ozaki_get_split() -> int:

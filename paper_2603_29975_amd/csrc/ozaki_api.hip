@@ -572,6 +572,30 @@ int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, 
   return rc;
 }
 
+// ---------------------------------------------------------------- blocked LU
+// C <- C - A B (complex, column-major blocks) through the emulated ZGEMM
+// (slices > 0, the current slice kind) or the native FP64 one (slices == 0).
+int lu_update(int slices, int64_t m, int64_t n, int64_t k, const double2 *A, int64_t lda,
+              const double2 *B, int64_t ldb, double2 *C, int64_t ldc) {
+  if (m <= 0 || n <= 0 || k <= 0) return OZAKI_OK;
+  if (slices > 0)
+    return emulated_gemm(true, 'N', 'N', m, n, k, -1.0, 0.0, A, lda, B, ldb, 1.0, 0.0, C, ldc,
+                         slices);
+  return native_gemm(true, 'N', 'N', m, n, k, -1.0, 0.0, A, lda, B, ldb, 1.0, 0.0, C, ldc);
+}
+
+int64_t *g_lu_flag[kMaxDev] = {};
+
+int lu_args(int64_t n, const void *A, int64_t lda, const void *ipiv, int64_t nb, int slices) {
+  if (n < 0) return -1;
+  if (A == nullptr && n > 0) return -2;
+  if (lda < std::max<int64_t>(1, n)) return -3;
+  if (ipiv == nullptr && n > 0) return -4;
+  if (nb < 1) return -5;
+  if (slices < 0 || slices > max_slices(split_b8())) return -6;
+  return 0;
+}
+
 // View of op(X) for the debug hooks (see ozaki.h for `side`).
 int debug_view(char kind, char side, char trans, int64_t rows, int64_t L, const void *X,
                int64_t ldx, View *v, bool *cplx) {
@@ -1435,6 +1459,70 @@ int ozaki2_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, ozak
                           beta.re, beta.im, C, ldc, moduli);
 }
 
+int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, int slices) {
+  int rc = lu_args(n, A, lda, ipiv, nb, slices);
+  if (rc) return rc;
+  if (n == 0) return OZAKI_OK;
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  if (g_lu_flag[dev] == nullptr && hipMalloc(&g_lu_flag[dev], sizeof(int64_t)) != hipSuccess) {
+    g_lu_flag[dev] = nullptr;
+    return OZAKI_ERR_ALLOC;
+  }
+  int64_t *flag = g_lu_flag[dev];
+  hipStream_t st = g.stream;
+  double2 *a = reinterpret_cast<double2 *>(A);
+  if ((rc = hip_rc(launch_set_i64(flag, n, st)))) return rc;
+  for (int64_t j0 = 0; j0 < n; j0 += nb) {
+    const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
+    for (int64_t c = j0; c < j1; ++c)
+      if ((rc = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return rc;
+    if ((rc = hip_rc(launch_laswp(a, lda, j0, j1, ipiv, 0, j0, st)))) return rc;
+    if ((rc = hip_rc(launch_laswp(a, lda, j0, j1, ipiv, j1, n, st)))) return rc;
+    if (j1 < n) {
+      // U12 = L11^-1 A12, then A22 -= L21 U12
+      if ((rc = hip_rc(launch_trsm(false, a + j0 + j0 * lda, lda, w, a + j0 + j1 * lda, lda, n - j1,
+                                   st))))
+        return rc;
+      if ((rc = lu_update(slices, n - j1, n - j1, w, a + j1 + j0 * lda, lda, a + j0 + j1 * lda, lda,
+                          a + j1 + j1 * lda, lda)))
+        return rc;
+    }
+  }
+  int64_t first_zero = n;
+  if (hipMemcpyAsync(&first_zero, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return OZAKI_ERR_HIP;
+  return first_zero < n ? OZAKI_ERR_SINGULAR : OZAKI_OK;
+}
+
+int ozaki_zgetri(int64_t n, const ozaki_z *LU, int64_t lda, const int64_t *ipiv, ozaki_z *X,
+                 int64_t ldx, int64_t nb, int slices) {
+  int rc = lu_args(n, LU, lda, ipiv, nb, slices);
+  if (rc) return rc;
+  if (X == nullptr && n > 0) return -7;  // X and ldx are checked as arguments 7 and 8
+  if (ldx < std::max<int64_t>(1, n)) return -8;
+  if (n == 0) return OZAKI_OK;
+  hipStream_t st = g.stream;
+  const double2 *lu = reinterpret_cast<const double2 *>(LU);
+  double2 *x = reinterpret_cast<double2 *>(X);
+  // X = P I, then Y = L^-1 X (blocks top down), then X = U^-1 Y (bottom up)
+  if ((rc = hip_rc(launch_identity(x, ldx, n, st)))) return rc;
+  if ((rc = hip_rc(launch_laswp(x, ldx, 0, n, ipiv, 0, n, st)))) return rc;
+  for (int64_t i0 = 0; i0 < n; i0 += nb) {
+    const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
+    if ((rc = hip_rc(launch_trsm(false, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return rc;
+    if ((rc = lu_update(slices, n - i1, n, w, lu + i1 + i0 * lda, lda, x + i0, ldx, x + i1, ldx)))
+      return rc;
+  }
+  for (int64_t i0 = (n - 1) / nb * nb; i0 >= 0; i0 -= nb) {
+    const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
+    if ((rc = hip_rc(launch_trsm(true, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return rc;
+    if ((rc = lu_update(slices, i0, n, w, lu + i0 * lda, lda, x + i0, ldx, x, ldx))) return rc;
+  }
+  return OZAKI_OK;
+}
+
 int ozaki2_moduli(int moduli, int32_t *out) {
   if (moduli < OZAKI2_MODULI_MIN || moduli > OZAKI2_MODULI_MAX) return -1;
   if (out == nullptr) return -2;
@@ -1792,6 +1880,13 @@ int ozaki_finalize(void) {
   g_sel.ws_bytes = 0;
   g_sel.plan_ws_bytes = 0;
   for (int d = 0; d < kMaxDev; ++d) {
+    if (g_lu_flag[d] != nullptr) {
+      int cur = 0;
+      if (hipGetDevice(&cur) != hipSuccess) rc = OZAKI_ERR_HIP;
+      if (hipSetDevice(d) != hipSuccess || hipFree(g_lu_flag[d]) != hipSuccess) rc = OZAKI_ERR_HIP;
+      (void)hipSetDevice(cur);
+      g_lu_flag[d] = nullptr;
+    }
     if (g_blas[d] == nullptr) continue;
     if (rocblas_destroy_handle(g_blas[d]) != rocblas_status_success) rc = OZAKI_ERR_INTERNAL;
     g_blas[d] = nullptr;
@@ -1810,6 +1905,7 @@ const char *ozaki_status_string(int status) {
     case OZAKI_ERR_INTERNAL: return "internal error";
     case OZAKI_ERR_NO_SELECTOR: return "automatic slice selection needs a loaded selector";
     case OZAKI_ERR_IO: return "tuning cache file missing, unwritable or malformed";
+    case OZAKI_ERR_SINGULAR: return "exactly zero pivot: the matrix is singular";
     default: return "unknown status";
   }
 }

@@ -202,6 +202,20 @@ struct CrtArgs {
 };
 hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
 
+// Blocked LU and inverse (see ozaki_lu.hip): one pivot column (pivot search,
+// swap over the panel columns [p0, p1), multipliers and panel update), row
+// interchanges ipiv[c0..c1) over the columns [q0, q1), a triangular solve
+// with nb x nb unit lower / non-unit upper T on ncols columns of X, the
+// identity, and a scalar store.
+hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
+                            int64_t *ipiv, int64_t *singular, hipStream_t st);
+hipError_t launch_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1, const int64_t *ipiv,
+                        int64_t q0, int64_t q1, hipStream_t st);
+hipError_t launch_trsm(bool upper, const double2 *T, int64_t ldt, int64_t nb, double2 *X,
+                       int64_t ldx, int64_t ncols, hipStream_t st);
+hipError_t launch_identity(double2 *X, int64_t ldx, int64_t n, hipStream_t st);
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st);
+
 // Native FP64 matrix-core GEMM.
 struct NativeArgs {
   View A;  // op(A): rows i, contraction l

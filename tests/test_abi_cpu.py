@@ -207,3 +207,16 @@ def test_ozaki2_size_limits_and_workspace():
     assert w14 >= 14 * (256 * 512 + 512 * 512 + 4 * 256 * 512)
     assert oz.ozaki2_workspace_bytes("z", 256, 256, 256, 16) > w14
     assert oz.ozaki2_workspace_bytes("q", 4, 4, 4, 14) == 0
+
+
+def test_lu_argument_errors():
+    big = 1 << 40
+    assert oz.ozaki_zgetrf(-1, big, 4, big, 64, 6) == -1
+    assert oz.ozaki_zgetrf(4, 0, 4, big, 64, 6) == -2
+    assert oz.ozaki_zgetrf(4, big, 3, big, 64, 6) == -3
+    assert oz.ozaki_zgetrf(4, big, 4, 0, 64, 6) == -4
+    assert oz.ozaki_zgetrf(4, big, 4, big, 0, 6) == -5
+    assert oz.ozaki_zgetrf(4, big, 4, big, 64, -1) == -6
+    assert oz.ozaki_zgetrf(0, 0, 1, 0, 64, 6) == 0
+    assert oz.ozaki_zgetri(4, big, 4, big, 0, 4, 64, 6) == -7
+    assert oz.ozaki_zgetri(4, big, 4, big, big, 3, 64, 6) == -8

@@ -1,0 +1,103 @@
+"""GPU parity of the blocked LU / inverse (ozaki_zgetrf, ozaki_zgetri) against
+the CPU model oracle/lu.py: factors, pivots and inverse bit for bit with
+emulated trailing updates (both slice kinds), close to it with the native FP64
+updates, and the inverse's error against the native path falling with s on a
+KKR-shaped matrix."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lu
+from tests.gpu_util import bits_equal, dev, host, mismatch_report, require_gpu, torch
+from workloads import kkr_operands
+
+import paper_2603_29975_amd as oz
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+    yield
+    torch.cuda.synchronize()
+    oz.ozaki_set_split("t7")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_lu_inv(A, nb, slices):
+    n = A.shape[0]
+    Ad, lda = dev(A)
+    ipiv = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+    rc = oz.ozaki_zgetrf(n, Ad, lda, ipiv, nb, slices)
+    assert rc == 0, oz.ozaki_status_string(rc)
+    Xd, ldx = dev(np.zeros((n, n), dtype=np.complex128))
+    rc = oz.ozaki_zgetri(n, Ad, lda, ipiv, Xd, ldx, nb, slices)
+    assert rc == 0, oz.ozaki_status_string(rc)
+    return host(Ad, n, n), ipiv.cpu().numpy()[:n], host(Xd, n, n)
+
+
+def _matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+
+@pytest.mark.parametrize("kind,s,n,nb", [("b8", 6, 200, 64), ("t7", 5, 200, 64), ("b8", 4, 130, 32),
+                                         ("t7", 7, 96, 96)])
+def test_lu_and_inverse_bit_exact(kind, s, n, nb):
+    A = _matrix(n, 1600 + n + s)
+    assert oz.ozaki_set_split(kind) == 0
+    _say("lu", kind, s, n, nb)
+    LU, ipiv, X = _gpu_lu_inv(A, nb, s)
+    upd = lu.update_model(kind, s)
+    LU_ref, ipiv_ref, singular = lu.zgetrf(A, nb, upd)
+    assert not singular
+    assert np.array_equal(ipiv, ipiv_ref)
+    assert bits_equal(LU, LU_ref), mismatch_report(LU, LU_ref)
+    X_ref = lu.zgetri(LU_ref, ipiv_ref, nb, upd)
+    assert bits_equal(X, X_ref), mismatch_report(X, X_ref)
+
+
+def test_lu_native_updates_close_to_the_model():
+    n, nb = 180, 64
+    A = _matrix(n, 1700)
+    LU, ipiv, X = _gpu_lu_inv(A, nb, 0)
+    LU_ref, ipiv_ref, _ = lu.zgetrf(A, nb, lu.update_model("native", 0))
+    assert np.array_equal(ipiv, ipiv_ref)
+    assert np.max(np.abs(LU - LU_ref)) <= 1e-12 * np.max(np.abs(LU_ref))
+    inv = np.linalg.inv(A)
+    assert np.max(np.abs(X - inv)) <= 1e-10 * np.max(np.abs(inv))
+
+
+def test_lu_singular_is_reported_and_tiny_sizes():
+    A = _matrix(40, 1710)
+    A[:, 7] = 0.0
+    Ad, lda = dev(A)
+    ipiv = torch.zeros(40, dtype=torch.int64, device="cuda")
+    assert oz.ozaki_zgetrf(40, Ad, lda, ipiv, 16, 6) == 8        # OZAKI_ERR_SINGULAR
+    for n in (1, 2, 5):
+        A1 = _matrix(n, 1720 + n)
+        LU, ipiv1, X = _gpu_lu_inv(A1, 4, 6)
+        LU_ref, ipiv_ref, _ = lu.zgetrf(A1, 4, lu.update_model("t7", 6))
+        assert np.array_equal(ipiv1, ipiv_ref) and bits_equal(LU, LU_ref)
+
+
+def test_kkr_inverse_error_falls_with_s():
+    # KKR-shaped I - T G of 16 blocks of 32: inverse through emulated updates
+    # against the same blocked algorithm with native FP64 updates
+    A, _ = kkr_operands(16, seed=1730)
+    _, _, X_nat = _gpu_lu_inv(A, 128, 0)
+    scale = np.max(np.abs(X_nat))
+    errs = {}
+    assert oz.ozaki_set_split("b8") == 0
+    for s in (3, 4, 5, 6, 7):
+        _, _, X = _gpu_lu_inv(A, 128, s)
+        errs[s] = float(np.max(np.abs(X - X_nat)) / scale)
+    _say("kkr 512 inverse error vs native (b8)", errs)
+    assert all(errs[s + 1] < errs[s] / 20 for s in (3, 4, 5, 6))
+    assert errs[7] < 1e-12
