@@ -36,13 +36,22 @@ __device__ __forceinline__ double cabs1(Z a) { return add_rn(fabs(a.re), fabs(a.
 
 // Pivot of column c (rows c..n-1), then the swap of rows c and the pivot row
 // over the panel columns [p0, p1). One workgroup of 1024 threads. A zero
-// pivot column is recorded in *singular (the smallest such column).
+// pivot column is recorded in *singular (the smallest such column). When
+// c > p0 the workgroup first stores the multipliers of column c - 1
+// (l_i = a_i,c-1 / a_c-1,c-1 for i >= c), which the panel update of that
+// column has finished using.
 __global__ void __launch_bounds__(1024) k_pivot_swap(double2 *A, int64_t lda, int64_t n, int64_t c,
                                                      int64_t p0, int64_t p1, int64_t *ipiv,
                                                      int64_t *singular) {
   __shared__ double sv[1024];
   __shared__ int64_t si[1024];
   const int t = threadIdx.x;
+  if (c > p0) {
+    const int64_t q = c - 1;
+    const Z p = ld(A + q + q * lda);
+    for (int64_t i = c + t; i < n; i += 1024) st(A + i + q * lda, zdiv(ld(A + i + q * lda), p));
+    __syncthreads();
+  }
   double best = -1.0;
   int64_t bi = n;
   for (int64_t i = c + t; i < n; i += 1024) {
@@ -81,16 +90,23 @@ __global__ void __launch_bounds__(1024) k_pivot_swap(double2 *A, int64_t lda, in
   }
 }
 
-// Row i > c of the panel: l = a_ic / a_cc is stored in place, then
-// a_ik -= l a_ck for the panel columns c < k < p1.
-__global__ void __launch_bounds__(256) k_panel_update(double2 *A, int64_t lda, int64_t n, int64_t c,
-                                                      int64_t p1) {
+// Panel update after the pivot of column c: a_ik -= (a_ic / a_cc) a_ck for
+// rows i > c and panel columns c < k < p1, one thread per element (each
+// recomputes its row's multiplier). The multipliers l_i = a_ic / a_cc are
+// stored afterwards: by the next column's pivot workgroup, or by k_panel_mult
+// for the last column of the panel.
+__global__ void __launch_bounds__(256) k_panel_update(double2 *A, int64_t lda, int64_t n, int64_t c) {
   const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = c + 1 + blockIdx.y;
   if (i >= n) return;
   const Z l = zdiv(ld(A + i + c * lda), ld(A + c + c * lda));
-  st(A + i + c * lda, l);
-  for (int64_t k = c + 1; k < p1; ++k)
-    st(A + i + k * lda, zsub(ld(A + i + k * lda), zmul(l, ld(A + c + k * lda))));
+  st(A + i + k * lda, zsub(ld(A + i + k * lda), zmul(l, ld(A + c + k * lda))));
+}
+
+__global__ void __launch_bounds__(256) k_panel_mult(double2 *A, int64_t lda, int64_t n, int64_t c) {
+  const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
 }
 
 // Row interchanges ipiv[c0..c1) applied in order to the columns [q0, q1) of A.
@@ -107,29 +123,44 @@ __global__ void __launch_bounds__(256) k_laswp(double2 *A, int64_t lda, int64_t 
   }
 }
 
-// X <- T^-1 X for the nb x nb triangle T (at T, leading dimension ldt) and
-// ncols columns of X: unit lower (forward: x_r -= t_rk x_k for k = 0..r-1)
-// or non-unit upper (backward: x_r = (x_r - sum_{k=r+1..nb-1} t_rk x_k) / t_rr,
-// the sum taken in increasing k). One thread per column.
+// X <- T^-1 X for the nb x nb triangle T (at T, leading dimension ldt) on
+// ncols columns of X, column-oriented: one workgroup per column, thread r
+// holds x_r. Unit lower (forward): for k = 0, 1, ..., x_k is final and every
+// x_r with r > k takes x_r -= t_rk x_k. Non-unit upper (backward): for
+// k = nb-1 down to 0, x_k = x_k / t_kk is final and every x_r with r < k takes
+// x_r -= t_rk x_k. Each x_r thus subtracts its terms in the order of k (forward:
+// increasing, backward: decreasing). One barrier per step; the final x_k goes
+// through LDS slot k.
 template <bool UPPER>
-__global__ void __launch_bounds__(256) k_trsm(const double2 *T, int64_t ldt, int64_t nb, double2 *X,
-                                              int64_t ldx, int64_t ncols) {
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= ncols) return;
-  double2 *x = X + col * ldx;
+__global__ void __launch_bounds__(1024) k_trsm(const double2 *T, int64_t ldt, int nb, double2 *X,
+                                               int64_t ldx) {
+  __shared__ double2 xs[1024];
+  const int r = threadIdx.x;
+  double2 *x = X + (int64_t)blockIdx.x * ldx;
+  Z xr = r < nb ? ld(x + r) : Z{0.0, 0.0};
   if constexpr (!UPPER) {
-    for (int64_t r = 1; r < nb; ++r) {
-      Z acc = ld(x + r);
-      for (int64_t k = 0; k < r; ++k) acc = zsub(acc, zmul(ld(T + r + k * ldt), ld(x + k)));
-      st(x + r, acc);
+    for (int k = 0; k < nb - 1; ++k) {
+      if (r == k) xs[k] = make_double2(xr.re, xr.im);
+      __syncthreads();
+      if (r > k && r < nb) {
+        const double2 v = xs[k];
+        xr = zsub(xr, zmul(ld(T + r + (int64_t)k * ldt), Z{v.x, v.y}));
+      }
     }
   } else {
-    for (int64_t r = nb - 1; r >= 0; --r) {
-      Z acc = ld(x + r);
-      for (int64_t k = r + 1; k < nb; ++k) acc = zsub(acc, zmul(ld(T + r + k * ldt), ld(x + k)));
-      st(x + r, zdiv(acc, ld(T + r + r * ldt)));
+    for (int k = nb - 1; k >= 0; --k) {
+      if (r == k) {
+        xr = zdiv(xr, ld(T + r + (int64_t)r * ldt));
+        xs[k] = make_double2(xr.re, xr.im);
+      }
+      __syncthreads();
+      if (r < k) {
+        const double2 v = xs[k];
+        xr = zsub(xr, zmul(ld(T + r + (int64_t)k * ldt), Z{v.x, v.y}));
+      }
     }
   }
+  if (r < nb) st(x + r, xr);
 }
 
 // X = identity (n x n, leading dimension ldx).
@@ -154,8 +185,13 @@ hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st) {
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st) {
   hipLaunchKernelGGL(k_pivot_swap, dim3(1), dim3(1024), 0, st, A, lda, n, c, p0, p1, ipiv, singular);
-  if (c + 1 < n)
-    hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1)), dim3(256), 0, st, A, lda, n, c, p1);
+  if (c + 1 < n) {
+    if (c + 1 < p1)
+      hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1), (unsigned)(p1 - c - 1)), dim3(256), 0,
+                         st, A, lda, n, c);
+    else
+      hipLaunchKernelGGL(k_panel_mult, dim3(blocks(n - c - 1)), dim3(256), 0, st, A, lda, n, c);
+  }
   return hipGetLastError();
 }
 
@@ -169,10 +205,12 @@ hipError_t launch_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1, const i
 hipError_t launch_trsm(bool upper, const double2 *T, int64_t ldt, int64_t nb, double2 *X,
                        int64_t ldx, int64_t ncols, hipStream_t st) {
   if (ncols <= 0 || nb <= 0) return hipSuccess;
+  if (nb > kLuMaxBlock || ncols > 0x7fffffffll) return hipErrorInvalidValue;
+  const dim3 block((unsigned)((nb + 63) / 64 * 64));
   if (upper)
-    hipLaunchKernelGGL(k_trsm<true>, dim3(blocks(ncols)), dim3(256), 0, st, T, ldt, nb, X, ldx, ncols);
+    hipLaunchKernelGGL(k_trsm<true>, dim3((unsigned)ncols), block, 0, st, T, ldt, (int)nb, X, ldx);
   else
-    hipLaunchKernelGGL(k_trsm<false>, dim3(blocks(ncols)), dim3(256), 0, st, T, ldt, nb, X, ldx, ncols);
+    hipLaunchKernelGGL(k_trsm<false>, dim3((unsigned)ncols), block, 0, st, T, ldt, (int)nb, X, ldx);
   return hipGetLastError();
 }
 
