@@ -174,16 +174,17 @@ size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int mo
  * ozaki_zgetrf: A (device, column-major, lda >= n) is overwritten by L (unit
  *   lower, below the diagonal) and U, with P A = L U; ipiv (device, n int64)
  *   receives the 0-based pivot row of each column (rows c and ipiv[c]
- *   exchanged in order). Panels of nb columns: pivot, swap and rank-one
- *   update per column inside the panel, the interchanges applied to the other
- *   columns, U12 = L11^-1 A12 (forward substitution, one thread per column),
- *   then A22 -= L21 U12. Returns OZAKI_ERR_SINGULAR (factors complete) if a
- *   pivot is exactly zero. Synchronises with the stream before returning.
+ *   exchanged in order). Panels of nb columns (1 <= nb <= 1024): pivot, swap
+ *   and rank-one update per column inside the panel, the interchanges applied
+ *   to the other columns, U12 = L11^-1 A12 (forward substitution), then
+ *   A22 -= L21 U12. Returns OZAKI_ERR_SINGULAR (factors complete) if a pivot
+ *   is exactly zero. Synchronises with the stream before returning.
  * ozaki_zgetri: X (device, ldx >= n, not overlapping LU) = A^-1 from the
  *   factors: X = P I; block rows of nb top down X_i = L_ii^-1 X_i, X_below -=
- *   L_below,i X_i; then bottom up X_i = U_ii^-1 X_i (backward substitution,
- *   the sum in increasing column order, then the quotient), X_above -=
- *   U_above,i X_i.
+ *   L_below,i X_i; then bottom up X_i = U_ii^-1 X_i, X_above -= U_above,i X_i.
+ * Substitutions are column-oriented: forward, x_r -= l_rk x_k for k = 0, 1,
+ * ... in turn; backward, for k = nb-1 down to 0, x_k /= u_kk and then
+ * x_r -= u_rk x_k for r < k (each x_r subtracts its terms in decreasing k).
  * Argument numbers: n 1, A/LU 2, lda 3, ipiv 4, nb 5, slices 6 (0..the slice
  * limit of the current kind), X 7, ldx 8.
  */

@@ -22,8 +22,9 @@ L3 factorization (right-looking, panels of nb columns): per column of the
    A22 <- update(A22, L21, U12), the GEMM model C - A B.
 L4 inverse: X = P I (the exchanges applied in order to the identity); block
    rows top down X_i = L_ii^-1 X_i, X_below <- update(X_below, L_below,i, X_i);
-   then bottom up X_i = U_ii^-1 X_i (x_r = (x_r - sum_{k>r} u_rk x_k) / u_rr,
-   the sum in increasing k), X_above <- update(X_above, U_above,i, X_i).
+   then bottom up X_i = U_ii^-1 X_i (for k = nb-1 down to 0: x_k = x_k / u_kk,
+   then x_r -= u_rk x_k for r < k; each x_r subtracts its terms in decreasing
+   k), X_above <- update(X_above, U_above,i, X_i).
 """
 from __future__ import annotations
 
@@ -70,13 +71,12 @@ def _trsm_lower_unit(TR, TI, XR, XI):
 
 def _trsm_upper(TR, TI, XR, XI):
     w = TR.shape[0]
-    for r in range(w - 1, -1, -1):
-        ar, ai = XR[r].copy(), XI[r].copy()
-        for k in range(r + 1, w):
+    for k in range(w - 1, -1, -1):
+        XR[k], XI[k] = _zdiv(XR[k], XI[k], TR[k, k], TI[k, k])
+        for r in range(k):
             pr, pi = _zmul(TR[r, k], TI[r, k], XR[k], XI[k])
-            ar = ar - pr
-            ai = ai - pi
-        XR[r], XI[r] = _zdiv(ar, ai, TR[r, r], TI[r, r])
+            XR[r] = XR[r] - pr
+            XI[r] = XI[r] - pi
 
 
 def zgetrf(A, nb: int, update):

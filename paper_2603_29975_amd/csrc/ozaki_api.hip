@@ -591,7 +591,7 @@ int lu_args(int64_t n, const void *A, int64_t lda, const void *ipiv, int64_t nb,
   if (A == nullptr && n > 0) return -2;
   if (lda < std::max<int64_t>(1, n)) return -3;
   if (ipiv == nullptr && n > 0) return -4;
-  if (nb < 1) return -5;
+  if (nb < 1 || nb > kLuMaxBlock) return -5;
   if (slices < 0 || slices > max_slices(split_b8())) return -6;
   return 0;
 }

@@ -207,6 +207,7 @@ hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
 // interchanges ipiv[c0..c1) over the columns [q0, q1), a triangular solve
 // with nb x nb unit lower / non-unit upper T on ncols columns of X, the
 // identity, and a scalar store.
+constexpr int64_t kLuMaxBlock = 1024;  // panel / block width limit (one thread per block row)
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st);
 hipError_t launch_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1, const int64_t *ipiv,
