@@ -249,9 +249,11 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //   3: as 2 with every fragment read of a block issued before its MFMAs
 //   4: 4 waves (2 x 2), tile 64 j' x 64 i, ring of two, two workgroups per CU
 //   5: as 4 with the reads of 3 (4 and 5 fall back to 2 for S >= 11)
+//   6: as 2 with two 32-row blocks of A' per wave (tile 128 j' x 128 i): each
+//      B' fragment feeds two MFMAs; S <= 6 only (else configuration 2)
 // A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
 // down the rows i, 1: along the columns j').
-constexpr int kNumCfg = 6;
+constexpr int kNumCfg = 7;
 
 template <int CFG>
 struct Pick;
@@ -266,6 +268,10 @@ struct Pick<1> {
 template <>
 struct Pick<2> {
   static constexpr int WJ = 4, WI = 2, IB = 1, RING = 2;
+};
+template <>
+struct Pick<3> {  // two 32-row blocks of A' per wave (S <= 6: the accumulators fit)
+  static constexpr int WJ = 4, WI = 2, IB = 2, RING = 2;
 };
 
 template <int S, int CFG>
@@ -296,6 +302,11 @@ hipError_t launch_s(int cfg, const GemmArgs &a, int num_cu, hipStream_t st) {
       } else {
         return launch_pick<S, 2>(a, num_cu, st);
       }
+    case 6:
+      if constexpr (S <= 6)
+        return launch_pick<S, 3>(a, num_cu, st);
+      else
+        return launch_pick<S, 2>(a, num_cu, st);
     default: return launch_pick<S, 0>(a, num_cu, st);
   }
 }
@@ -315,7 +326,8 @@ size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
   // the largest per-workgroup carry space over the configurations, so that a
   // plan is valid whichever configuration runs
   (void)cfg;
-  const int waves = std::max(waves_of<0>(), std::max(waves_of<1>(), waves_of<2>()));
+  const int waves =
+      std::max(std::max(waves_of<0>(), waves_of<1>()), std::max(waves_of<2>(), waves_of<3>()));
   return (size_t)num_cu * waves * (size_t)S * 1024 * sizeof(int64_t);
 }
 
@@ -330,6 +342,15 @@ int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
       if (S <= 10) {
         BJ = 64;
         BI = 64;
+      } else {  // launched as configuration 2
+        BJ = 32 * Pick<2>::WJ;
+        BI = 32 * Pick<2>::WI * Pick<2>::IB;
+      }
+      break;
+    case 6:
+      if (S <= 6) {
+        BJ = 32 * Pick<3>::WJ;
+        BI = 32 * Pick<3>::WI * Pick<3>::IB;
       } else {  // launched as configuration 2
         BJ = 32 * Pick<2>::WJ;
         BI = 32 * Pick<2>::WI * Pick<2>::IB;
