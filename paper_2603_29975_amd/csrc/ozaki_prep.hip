@@ -228,32 +228,32 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
   }
 
   if constexpr (B8) {
-    // 8-bit balanced slices: X = trunc(x 2^(8S - 2)) with the sign of x, then
-    // its balanced base-256 digits d in [-128, 127] from the least significant
-    // one up (d = ((X + 128) mod 256) - 128, X <- (X - d) / 256); slice p holds
-    // the digit of weight 256^(S - p). Every value is split as it stands, so
+    // 8-bit balanced slices: X = trunc(x 2^(8S - 2)) with the sign of x, and
+    // its balanced base-256 digits d_p in [-128, 127] (slice p holds the digit
+    // of weight 256^(S - p)). With Y = X + 128 (256^S - 1) / 255, which lies in
+    // [0, 256^S) because |X| < 2^(8S - 2), the plain base-256 bytes b_p of Y
+    // are d_p + 128: the same digits as the recurrence d = ((X + 128) mod 256)
+    // - 128, X <- (X - d) / 256, read off as bytes, with d_p = b_p - 128 being
+    // b_p XOR 0x80 in two's complement. Every value is split as it stands, so
     // the -Im row of complex B gets the digits of -Im.
     static_assert(SC >= 1 && SC <= 8, "8-bit slices need 8S - 2 <= 62");
-    int64_t X[16];
+    constexpr uint64_t kBias = 0x8080808080808080ull >> (8 * (8 - SC));  // 128 (256^S - 1) / 255
+    uint64_t Y[16];
 #pragma unroll
     for (int x = 0; x < 16; ++x) {
-      const int64_t u = (int64_t)top_nbits<8 * SC - 2>(sg[x]);
-      X[x] = sg[x].neg ? -u : u;
+      const uint64_t u = top_nbits<8 * SC - 2>(sg[x]);
+      Y[x] = (sg[x].neg ? (0ull - u) : u) + kBias;  // mod 2^64; the true value is in [0, 256^S)
     }
 #pragma unroll
     for (int p = SC; p >= 1; --p) {
+      const int sh = 8 * (SC - p);
       uint32_t w[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         uint32_t word = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          int64_t &xv = X[4 * q + b];
-          const int d = (int)((xv + 128) & 255) - 128;
-          xv = (xv - d) >> 8;
-          word |= ((uint32_t)d & 0xffu) << (8 * b);
-        }
-        w[q] = word;
+        for (int b = 0; b < 4; ++b) word |= ((uint32_t)(Y[4 * q + b] >> sh) & 0xffu) << (8 * b);
+        w[q] = word ^ 0x80808080u;
       }
       int8_t *dst = out + frag_offset(p - 1, rp, kp0, nrb, nkb);
       *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
