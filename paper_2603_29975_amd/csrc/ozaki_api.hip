@@ -307,8 +307,10 @@ int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t
   int8_t *SB = reinterpret_cast<int8_t *>(ws + p.off_SB);
   int rc;
   int mk = phase_begin(OZAKI_PHASE_SCAN, st);
-  if ((rc = hip_rc(launch_fill_i32(codeA, p.m, 0, st)))) return rc;
-  if ((rc = hip_rc(launch_fill_i32(codeB, p.n, 0, st)))) return rc;
+  // codeA and codeB lie back to back (codeB at off_codeB): one fill zeroes both
+  if ((rc = hip_rc(launch_fill_i32(codeA, (int64_t)((p.off_codeB - p.off_codeA) / sizeof(int)) + p.n,
+                                   0, st))))
+    return rc;
   if ((rc = hip_rc(launch_scan(va, p.cplx, codeA, st)))) return rc;
   if ((rc = hip_rc(launch_scan(vb, p.cplx, codeB, st)))) return rc;
   phase_end(mk, st);
@@ -522,8 +524,9 @@ int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, 
   hipStream_t st = g.stream;
 
   int mk = phase_begin(OZAKI_PHASE_SCAN, st);
-  if ((rc = hip_rc(launch_fill_i32(codeA, m, 0, st)))) return rc;
-  if ((rc = hip_rc(launch_fill_i32(codeB, n, 0, st)))) return rc;
+  if ((rc = hip_rc(launch_fill_i32(codeA, (int64_t)((p.off_codeB - p.off_codeA) / sizeof(int)) + n,
+                                   0, st))))
+    return rc;
   if ((rc = hip_rc(launch_scan(va, cplx, codeA, st)))) return rc;
   if ((rc = hip_rc(launch_scan(vb, cplx, codeB, st)))) return rc;
   phase_end(mk, st);
