@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--workload", default="kkr2048",
                     choices=["kkr2048", "binade256", "ill4096", "ill16384", "batched512",
                              "selector512", "kkrinv2048"])
-    ap.add_argument("--nb", type=int, default=256, help="kkrinv2048: LU panel width")
+    ap.add_argument("--nb", type=int, default=128, help="kkrinv2048: LU panel width")
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2603_29975_amd",
                                                          "selector_weights.npz"),
                     help="trained selector weights (selector512 workload)")

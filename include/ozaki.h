@@ -170,7 +170,8 @@ size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int mo
  * operation written out as separately rounded real operations:
  *   product  (ar br - ai bi, ar bi + ai br)
  *   quotient d = br^2 + bi^2, ((ar br + ai bi) / d, (ai br - ar bi) / d)
- *   pivot    the first row of the largest |Re| + |Im| in the column
+ *   pivot    the first row of the largest |Re| + |Im| in the column (a NaN
+ *            counts as the largest)
  * ozaki_zgetrf: A (device, column-major, lda >= n) is overwritten by L (unit
  *   lower, below the diagonal) and U, with P A = L U; ipiv (device, n int64)
  *   receives the 0-based pivot row of each column (rows c and ipiv[c]
@@ -178,9 +179,10 @@ size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int mo
  *   and rank-one update per column inside the panel, the interchanges applied
  *   to the other columns, U12 = L11^-1 A12 (forward substitution), then
  *   A22 -= L21 U12. Returns OZAKI_ERR_SINGULAR (factors complete) if a pivot
- *   is exactly zero. Synchronises with the stream before returning.
+ *   is exactly zero or NaN. Synchronises with the stream before returning.
  * ozaki_zgetri: X (device, ldx >= n, not overlapping LU) = A^-1 from the
- *   factors: X = P I; block rows of nb top down X_i = L_ii^-1 X_i, X_below -=
+ *   factors: X = P I (an ipiv entry outside [c, n) counts as no exchange);
+ *   block rows of nb top down X_i = L_ii^-1 X_i, X_below -=
  *   L_below,i X_i; then bottom up X_i = U_ii^-1 X_i, X_above -= U_above,i X_i.
  * Substitutions are column-oriented: forward, x_r -= l_rk x_k for k = 0, 1,
  * ... in turn; backward, for k = nb-1 down to 0, x_k /= u_kk and then

@@ -12,8 +12,9 @@ L1 arithmetic: every complex product is (ar br - ai bi, ar bi + ai br) and
    every quotient a / b is ((ar br + ai bi) / d, (ai br - ar bi) / d) with
    d = br br + bi bi, each real operation rounded on its own.
 L2 pivoting: in column c the pivot is the first row of rows c..n-1 with the
-   largest |Re| + |Im| (the measure of the reference LAPACK's izamax); rows c
-   and pivot are exchanged.
+   largest |Re| + |Im| (the measure of the reference LAPACK's izamax; a NaN
+   counts as the largest, as numpy's argmax takes it); rows c and pivot are
+   exchanged.
 L3 factorization (right-looking, panels of nb columns): per column of the
    panel, pivot and exchange within the panel columns, multipliers
    l_i = a_ic / a_cc stored in place, a_ik -= l_i a_ck for the later panel

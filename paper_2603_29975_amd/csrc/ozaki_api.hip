@@ -587,7 +587,21 @@ int lu_update(int slices, int64_t m, int64_t n, int64_t k, const double2 *A, int
   return native_gemm(true, 'N', 'N', m, n, k, -1.0, 0.0, A, lda, B, ldb, 1.0, 0.0, C, ldc);
 }
 
+// Per device: the singular-column flag (one int64), then the row
+// interchange slots (kLuPairWords int64).
 int64_t *g_lu_flag[kMaxDev] = {};
+
+int lu_workspace(int64_t **out) {
+  int dev = 0;
+  if (int rc = current_device(&dev)) return rc;
+  if (g_lu_flag[dev] == nullptr &&
+      hipMalloc(&g_lu_flag[dev], sizeof(int64_t) * (1 + kLuPairWords)) != hipSuccess) {
+    g_lu_flag[dev] = nullptr;
+    return OZAKI_ERR_ALLOC;
+  }
+  *out = g_lu_flag[dev];
+  return OZAKI_OK;
+}
 
 int lu_args(int64_t n, const void *A, int64_t lda, const void *ipiv, int64_t nb, int slices) {
   if (n < 0) return -1;
@@ -1466,13 +1480,9 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
   int rc = lu_args(n, A, lda, ipiv, nb, slices);
   if (rc) return rc;
   if (n == 0) return OZAKI_OK;
-  int dev = 0;
-  if ((rc = current_device(&dev))) return rc;
-  if (g_lu_flag[dev] == nullptr && hipMalloc(&g_lu_flag[dev], sizeof(int64_t)) != hipSuccess) {
-    g_lu_flag[dev] = nullptr;
-    return OZAKI_ERR_ALLOC;
-  }
-  int64_t *flag = g_lu_flag[dev];
+  int64_t *flag = nullptr;
+  if ((rc = lu_workspace(&flag))) return rc;
+  int64_t *pairs = flag + 1;
   hipStream_t st = g.stream;
   double2 *a = reinterpret_cast<double2 *>(A);
   if ((rc = hip_rc(launch_set_i64(flag, n, st)))) return rc;
@@ -1480,8 +1490,8 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
     const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
     for (int64_t c = j0; c < j1; ++c)
       if ((rc = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return rc;
-    if ((rc = hip_rc(launch_laswp(a, lda, j0, j1, ipiv, 0, j0, st)))) return rc;
-    if ((rc = hip_rc(launch_laswp(a, lda, j0, j1, ipiv, j1, n, st)))) return rc;
+    if ((rc = hip_rc(launch_swap_pairs(ipiv, j0, j1, n, pairs, st)))) return rc;
+    if ((rc = hip_rc(launch_apply_pairs(a, lda, w, pairs, 0, j0, j1, n, st)))) return rc;
     if (j1 < n) {
       // U12 = L11^-1 A12, then A22 -= L21 U12
       if ((rc = hip_rc(launch_trsm(false, a + j0 + j0 * lda, lda, w, a + j0 + j1 * lda, lda, n - j1,
@@ -1506,12 +1516,20 @@ int ozaki_zgetri(int64_t n, const ozaki_z *LU, int64_t lda, const int64_t *ipiv,
   if (X == nullptr && n > 0) return -7;  // X and ldx are checked as arguments 7 and 8
   if (ldx < std::max<int64_t>(1, n)) return -8;
   if (n == 0) return OZAKI_OK;
+  int64_t *flag = nullptr;
+  if ((rc = lu_workspace(&flag))) return rc;
+  int64_t *pairs = flag + 1;
   hipStream_t st = g.stream;
   const double2 *lu = reinterpret_cast<const double2 *>(LU);
   double2 *x = reinterpret_cast<double2 *>(X);
-  // X = P I, then Y = L^-1 X (blocks top down), then X = U^-1 Y (bottom up)
+  // X = P I (the interchanges in blocks of nb, in order), then Y = L^-1 X
+  // (blocks top down), then X = U^-1 Y (bottom up)
   if ((rc = hip_rc(launch_identity(x, ldx, n, st)))) return rc;
-  if ((rc = hip_rc(launch_laswp(x, ldx, 0, n, ipiv, 0, n, st)))) return rc;
+  for (int64_t i0 = 0; i0 < n; i0 += nb) {
+    const int64_t i1 = std::min(n, i0 + nb);
+    if ((rc = hip_rc(launch_swap_pairs(ipiv, i0, i1, n, pairs, st)))) return rc;
+    if ((rc = hip_rc(launch_apply_pairs(x, ldx, i1 - i0, pairs, 0, n, 0, 0, st)))) return rc;
+  }
   for (int64_t i0 = 0; i0 < n; i0 += nb) {
     const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
     if ((rc = hip_rc(launch_trsm(false, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return rc;

@@ -203,15 +203,20 @@ struct CrtArgs {
 hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
 
 // Blocked LU and inverse (see ozaki_lu.hip): one pivot column (pivot search,
-// swap over the panel columns [p0, p1), multipliers and panel update), row
-// interchanges ipiv[c0..c1) over the columns [q0, q1), a triangular solve
-// with nb x nb unit lower / non-unit upper T on ncols columns of X, the
-// identity, and a scalar store.
+// swap over the panel columns [p0, p1), multipliers and panel update); the
+// row interchanges ipiv[c0..c1) (c1 - c0 <= kLuMaxBlock) turned into
+// destination/source row slots in `pairs` (kLuPairWords int64: destinations,
+// then sources, at offset 2 * kLuMaxBlock) and applied to the columns
+// [q0, q1) and [q2, q3); a triangular solve with nb x nb unit lower /
+// non-unit upper T on ncols columns of X; the identity; a scalar store.
 constexpr int64_t kLuMaxBlock = 1024;  // panel / block width limit (one thread per block row)
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st);
-hipError_t launch_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1, const int64_t *ipiv,
-                        int64_t q0, int64_t q1, hipStream_t st);
+constexpr int64_t kLuPairWords = 4 * kLuMaxBlock;
+hipError_t launch_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1, int64_t n,
+                             int64_t *pairs, hipStream_t st);
+hipError_t launch_apply_pairs(double2 *A, int64_t lda, int64_t w, const int64_t *pairs, int64_t q0,
+                              int64_t q1, int64_t q2, int64_t q3, hipStream_t st);
 hipError_t launch_trsm(bool upper, const double2 *T, int64_t ldt, int64_t nb, double2 *X,
                        int64_t ldx, int64_t ncols, hipStream_t st);
 hipError_t launch_identity(double2 *X, int64_t ldx, int64_t n, hipStream_t st);

@@ -7,7 +7,8 @@
 // for bit:
 //   product   (ar br - ai bi, ar bi + ai br)
 //   quotient  d = br br + bi bi, ((ar br + ai bi) / d, (ai br - ar bi) / d)
-//   pivot     the first row of the largest |Re| + |Im| in the column
+//   pivot     the first row of the largest |Re| + |Im| in the column (NaN
+//             counts as the largest)
 #include "ozaki_internal.hpp"
 
 namespace oz {
@@ -34,58 +35,108 @@ __device__ __forceinline__ Z zdiv(Z a, Z b) {
 }
 __device__ __forceinline__ double cabs1(Z a) { return add_rn(fabs(a.re), fabs(a.im)); }
 
+// Pivot order: the larger |Re| + |Im| wins, a NaN counts as larger than any
+// number, and equal values (or two NaNs) go to the lower row.
+__device__ __forceinline__ bool beats(double v, int64_t i, double bv, int64_t bi) {
+  const bool vn = v != v, bn = bv != bv;
+  if (vn != bn) return vn;
+  if (vn) return i < bi;
+  return v > bv || (v == bv && i < bi);
+}
+
 // Pivot of column c (rows c..n-1), then the swap of rows c and the pivot row
-// over the panel columns [p0, p1). One workgroup of 1024 threads. A zero
-// pivot column is recorded in *singular (the smallest such column). When
-// c > p0 the workgroup first stores the multipliers of column c - 1
+// over the panel columns [p0, p1). One workgroup of 256 threads. When c > p0
+// the workgroup also stores the multipliers of column c - 1
 // (l_i = a_i,c-1 / a_c-1,c-1 for i >= c), which the panel update of that
-// column has finished using.
-__global__ void __launch_bounds__(1024) k_pivot_swap(double2 *A, int64_t lda, int64_t n, int64_t c,
-                                                     int64_t p0, int64_t p1, int64_t *ipiv,
-                                                     int64_t *singular) {
-  __shared__ double sv[1024];
-  __shared__ int64_t si[1024];
+// column has finished using. Rows go in batches of 8 per thread, the loads of
+// both columns first so their latencies overlap; the waves reduce with
+// cross-lane shuffles and every thread reduces the 4 wave results itself.
+// The reduction's barrier orders the multiplier stores before the swap reads
+// them. A pivot that is zero or NaN is recorded in *singular (the smallest
+// such column).
+__global__ void __launch_bounds__(256) k_pivot_swap(double2 *A, int64_t lda, int64_t n, int64_t c,
+                                                    int64_t p0, int64_t p1, int64_t *ipiv,
+                                                    int64_t *singular) {
+  constexpr int kB = 8;
+  __shared__ double sv[4];
+  __shared__ int64_t si[4];
   const int t = threadIdx.x;
-  if (c > p0) {
-    const int64_t q = c - 1;
-    const Z p = ld(A + q + q * lda);
-    for (int64_t i = c + t; i < n; i += 1024) st(A + i + q * lda, zdiv(ld(A + i + q * lda), p));
-    __syncthreads();
-  }
+  const bool mult = c > p0;
+  const int64_t q = c - 1;
+  const Z dq = mult ? ld(A + q + q * lda) : Z{1.0, 0.0};
   double best = -1.0;
   int64_t bi = n;
-  for (int64_t i = c + t; i < n; i += 1024) {
-    const double v = cabs1(ld(A + i + c * lda));
-    if (v > best) {  // rows visited in increasing order: ties keep the first
-      best = v;
-      bi = i;
-    }
-  }
-  sv[t] = best;
-  si[t] = bi;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) {
-      const double vo = sv[t + w];
-      const int64_t io = si[t + w];
-      if (vo > sv[t] || (vo == sv[t] && io < si[t])) {
-        sv[t] = vo;
-        si[t] = io;
+  for (int64_t i0 = c + t; i0 < n; i0 += 256 * kB) {
+    Z v[kB], m[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int64_t i = i0 + 256 * j;
+      if (i < n) {
+        v[j] = ld(A + i + c * lda);
+        if (mult) m[j] = ld(A + i + q * lda);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int64_t i = i0 + 256 * j;
+      if (i < n) {
+        if (mult) st(A + i + q * lda, zdiv(m[j], dq));
+        const double a = cabs1(v[j]);
+        if (beats(a, i, best, bi)) {  // rows of a thread in increasing order
+          best = a;
+          bi = i;
+        }
+      }
+    }
   }
-  const int64_t piv = si[0];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o);
+    const int64_t oi = __shfl_xor(bi, o);
+    if (beats(ov, oi, best, bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  if ((t & 63) == 0) {
+    sv[t >> 6] = best;
+    si[t >> 6] = bi;
+  }
+  __syncthreads();
+  best = sv[0];
+  bi = si[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w)
+    if (beats(sv[w], si[w], best, bi)) {
+      best = sv[w];
+      bi = si[w];
+    }
+  // row c itself takes part, so bi is a row of [c, n) (any value or NaN beats -1)
+  const int64_t piv = bi;
   if (t == 0) {
     ipiv[c] = piv;
-    if (!(sv[0] > 0.0)) atomicMin(reinterpret_cast<unsigned long long *>(singular),
-                                  (unsigned long long)c);
+    if (!(best > 0.0)) atomicMin(reinterpret_cast<unsigned long long *>(singular),
+                                 (unsigned long long)c);
   }
   if (piv != c) {
-    for (int64_t k = p0 + t; k < p1; k += 1024) {
-      const Z a = ld(A + c + k * lda), b = ld(A + piv + k * lda);
-      st(A + c + k * lda, b);
-      st(A + piv + k * lda, a);
+    for (int64_t k0 = p0 + t; k0 < p1; k0 += 256 * 4) {
+      Z x[4], y[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t k = k0 + 256 * j;
+        if (k < p1) {
+          x[j] = ld(A + c + k * lda);
+          y[j] = ld(A + piv + k * lda);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t k = k0 + 256 * j;
+        if (k < p1) {
+          st(A + c + k * lda, y[j]);
+          st(A + piv + k * lda, x[j]);
+        }
+      }
     }
   }
 }
@@ -109,18 +160,91 @@ __global__ void __launch_bounds__(256) k_panel_mult(double2 *A, int64_t lda, int
   st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
 }
 
-// Row interchanges ipiv[c0..c1) applied in order to the columns [q0, q1) of A.
-__global__ void __launch_bounds__(256) k_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1,
-                                               const int64_t *ipiv, int64_t q0, int64_t q1) {
-  const int64_t k = q0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= q1) return;
-  for (int64_t c = c0; c < c1; ++c) {
-    const int64_t p = ipiv[c];
-    if (p == c) continue;
-    const Z a = ld(A + c + k * lda), b = ld(A + p + k * lda);
-    st(A + c + k * lda, b);
-    st(A + p + k * lda, a);
+// The row interchanges ipiv[c0..c1) (rows c and ipiv[c] exchanged for c =
+// c0, c0+1, ... in turn, ipiv[c] in [c, n)) as one gather: row dst[e] of the
+// result is row src[e] of the input, for the w = c1 - c0 <= 1024 slots
+// e = t (dst = c0 + t) and the slots e = w + t (dst = ipiv[c0 + t] when that
+// row lies below c1 and no later interchange names it; dst = -1 otherwise).
+// Derivation, with t' < t meaning an earlier interchange: row c0 + t is final
+// after interchange t, when it takes what row ipiv[c0 + t] held just before.
+// Let E(t) be what row c0 + t held just before interchange t: its own row if
+// no earlier interchange named it, else E of the latest one that did (a chain
+// of decreasing t, resolved by pointer jumping). Row x >= c0 + t holds, just
+// before interchange t, E(t') for the latest t' < t with ipiv[c0 + t'] = x, or
+// x itself if there is none. One workgroup of 1024 threads, thread t for
+// interchange t, each scanning the w pivots in LDS. An entry outside [c, n)
+// counts as no interchange.
+__global__ void __launch_bounds__(1024) k_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1,
+                                                     int64_t n, int64_t *dst, int64_t *src) {
+  __shared__ int64_t piv[1024];
+  __shared__ int nxt[1024];
+  const int w = (int)(c1 - c0);
+  const int t = threadIdx.x;
+  int64_t pt = -1;
+  if (t < w) {
+    pt = ipiv[c0 + t];
+    if (pt < c0 + t || pt >= n) pt = c0 + t;
+    piv[t] = pt;
   }
+  __syncthreads();
+  int named_by = -1, prev_same = -1;
+  bool last = true;
+  if (t < w) {
+    for (int u = 0; u < w; ++u) {
+      const int64_t pu = piv[u];
+      if (u < t) {
+        if (pu == c0 + t) named_by = u;
+        if (pu == pt) prev_same = u;
+      } else if (u > t && pu == pt) {
+        last = false;
+      }
+    }
+  }
+  nxt[t] = named_by >= 0 ? named_by : t;
+  __syncthreads();
+  for (int r = 0; r < 10; ++r) {  // chains are shorter than 1024 = 2^10
+    const int v = nxt[nxt[t]];
+    __syncthreads();
+    nxt[t] = v;
+    __syncthreads();
+  }
+  if (t < w) {
+    dst[t] = c0 + t;
+    src[t] = prev_same >= 0 ? c0 + nxt[prev_same] : pt;
+    const bool below = pt >= c1 && last;
+    dst[w + t] = below ? pt : -1;
+    src[w + t] = below ? c0 + nxt[t] : -1;
+  }
+}
+
+// Applies the gather of k_swap_pairs (2w <= 2048 slots) to the columns
+// [q0, q1) and [q2, q3) of A, one workgroup per column: every thread reads its
+// slots' source rows, waits for them, and after the barrier writes them.
+__global__ void __launch_bounds__(256) k_apply_pairs(double2 *A, int64_t lda, int slots,
+                                                     const int64_t *dst, const int64_t *src,
+                                                     int64_t q0, int64_t q1, int64_t q2) {
+  const int64_t b = blockIdx.x;
+  const int64_t k = b < q1 - q0 ? q0 + b : q2 + (b - (q1 - q0));
+  double2 *col = A + k * lda;
+  double2 v[8];
+  int64_t d[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    d[j] = -1;
+    if (e < slots) {
+      const int64_t de = dst[e], se = src[e];
+      if (de >= 0 && de != se) {
+        d[j] = de;
+        v[j] = col[se];
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (d[j] >= 0) col[d[j]] = v[j];
 }
 
 // X <- T^-1 X for the nb x nb triangle T (at T, leading dimension ldt) on
@@ -184,7 +308,7 @@ hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st) {
 
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st) {
-  hipLaunchKernelGGL(k_pivot_swap, dim3(1), dim3(1024), 0, st, A, lda, n, c, p0, p1, ipiv, singular);
+  hipLaunchKernelGGL(k_pivot_swap, dim3(1), dim3(256), 0, st, A, lda, n, c, p0, p1, ipiv, singular);
   if (c + 1 < n) {
     if (c + 1 < p1)
       hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1), (unsigned)(p1 - c - 1)), dim3(256), 0,
@@ -195,10 +319,23 @@ hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64
   return hipGetLastError();
 }
 
-hipError_t launch_laswp(double2 *A, int64_t lda, int64_t c0, int64_t c1, const int64_t *ipiv,
-                        int64_t q0, int64_t q1, hipStream_t st) {
-  if (q1 <= q0 || c1 <= c0) return hipSuccess;
-  hipLaunchKernelGGL(k_laswp, dim3(blocks(q1 - q0)), dim3(256), 0, st, A, lda, c0, c1, ipiv, q0, q1);
+hipError_t launch_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1, int64_t n,
+                             int64_t *pairs, hipStream_t st) {
+  if (c1 <= c0) return hipSuccess;
+  if (c1 - c0 > kLuMaxBlock) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3(1024), 0, st, ipiv, c0, c1, n, pairs,
+                     pairs + 2 * kLuMaxBlock);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_pairs(double2 *A, int64_t lda, int64_t w, const int64_t *pairs, int64_t q0,
+                              int64_t q1, int64_t q2, int64_t q3, hipStream_t st) {
+  const int64_t cols = std::max<int64_t>(0, q1 - q0) + std::max<int64_t>(0, q3 - q2);
+  if (cols == 0 || w <= 0) return hipSuccess;
+  if (w > kLuMaxBlock || cols > 0x7fffffffll) return hipErrorInvalidValue;
+  if (q1 < q0) q1 = q0;
+  hipLaunchKernelGGL(k_apply_pairs, dim3((unsigned)cols), dim3(256), 0, st, A, lda, (int)(2 * w),
+                     pairs, pairs + 2 * kLuMaxBlock, q0, q1, q2);
   return hipGetLastError();
 }
 

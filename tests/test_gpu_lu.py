@@ -101,3 +101,51 @@ def test_kkr_inverse_error_falls_with_s():
     _say("kkr 512 inverse error vs native (b8)", errs)
     assert all(errs[s + 1] < errs[s] / 20 for s in (3, 4, 5, 6))
     assert errs[7] < 1e-12
+
+
+def _sequential_interchanges(n, ipiv):
+    perm = np.arange(n)
+    for c in range(n):
+        p = int(ipiv[c])
+        perm[c], perm[p] = perm[p], perm[c]
+    return perm
+
+
+@pytest.mark.parametrize("n,nb,seed", [(300, 64, 1740), (257, 1, 1741), (96, 96, 1742), (1030, 1024, 1743)])
+def test_interchanges_as_gathers(n, nb, seed):
+    # with LU = I (L and U both the identity) the inverse is X = P I exactly:
+    # row r of X is row perm[r] of I for the interchanges applied in turn.
+    # Pivot sequences with chains, repeats and rows far below the block.
+    rng = np.random.default_rng(seed)
+    ipiv = np.arange(n, dtype=np.int64)
+    for c in range(n):
+        mode = rng.integers(0, 4)
+        if mode == 1:
+            ipiv[c] = int(rng.integers(c, min(n, c + 3)))
+        elif mode >= 2:
+            ipiv[c] = int(rng.integers(c, n))
+    Id, lda = dev(np.eye(n, dtype=np.complex128))
+    piv = torch.from_numpy(ipiv).to("cuda")
+    Xd, ldx = dev(np.zeros((n, n), dtype=np.complex128))
+    _say("interchanges", n, nb)
+    rc = oz.ozaki_zgetri(n, Id, lda, piv, Xd, ldx, nb, 0)
+    assert rc == 0, oz.ozaki_status_string(rc)
+    X = host(Xd, n, n)
+    perm = _sequential_interchanges(n, ipiv)
+    assert np.array_equal(X, np.eye(n)[perm])
+
+
+def test_nan_entry_is_the_pivot_like_the_model():
+    # a NaN counts as the largest |Re| + |Im| (the first NaN row wins), so every
+    # pivot stays inside the column and the factorization reports a singular pivot
+    n, nb = 40, 16
+    A = _matrix(n, 1750)
+    A[5, 3] = complex(np.nan, 0.0)
+    assert oz.ozaki_set_split("t7") == 0
+    Ad, lda = dev(A)
+    ipiv = torch.zeros(n, dtype=torch.int64, device="cuda")
+    _say("lu nan pivot")
+    assert oz.ozaki_zgetrf(n, Ad, lda, ipiv, nb, 6) == 8        # OZAKI_ERR_SINGULAR
+    _, ipiv_ref, singular = lu.zgetrf(A, nb, lu.update_model("t7", 6))
+    assert singular
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_ref)

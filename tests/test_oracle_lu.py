@@ -49,3 +49,16 @@ def test_emulated_updates_converge_to_fp64(kind):
     # condition number ~3e3: the inverse carries the product error times ~cond
     assert all(errs[s + 1] < errs[s] / 20 for s in (3, 4, 5, 6))
     assert errs[7] < (1e-10 if kind == "t7" else 1e-12)
+
+
+def test_nan_counts_as_the_largest_pivot():
+    # reading L2 for non-finite input: the first NaN row of the column is the
+    # pivot, and the factorization is flagged singular
+    A = _matrix(12, 1760)
+    A[7, 0] = complex(np.nan, 1.0)
+    A[9, 0] = complex(0.0, np.nan)
+    A[4, 0] = 1e300
+    _, ipiv, singular = lu.zgetrf(A, 4, lu.update_model("native", 0))
+    assert singular
+    assert ipiv[0] == 7
+    assert all(ipiv[c] == c for c in range(1, 12))   # NaN everywhere below: the first row
