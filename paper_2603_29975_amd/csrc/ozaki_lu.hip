@@ -247,6 +247,15 @@ __global__ void __launch_bounds__(256) k_apply_pairs(double2 *A, int64_t lda, in
     if (d[j] >= 0) col[d[j]] = v[j];
 }
 
+// Wait for this wave's LDS accesses, then the workgroup barrier alone: no
+// wait for global loads, so prefetches stay in flight across it.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+#pragma clang diagnostic pop
+
 // X <- T^-1 X for the nb x nb triangle T (at T, leading dimension ldt) on
 // ncols columns of X, column-oriented: one workgroup per column, thread r
 // holds x_r. Unit lower (forward): for k = 0, 1, ..., x_k is final and every
@@ -254,33 +263,51 @@ __global__ void __launch_bounds__(256) k_apply_pairs(double2 *A, int64_t lda, in
 // k = nb-1 down to 0, x_k = x_k / t_kk is final and every x_r with r < k takes
 // x_r -= t_rk x_k. Each x_r thus subtracts its terms in the order of k (forward:
 // increasing, backward: decreasing). One barrier per step; the final x_k goes
-// through LDS slot k.
+// through LDS slot k. Thread r loads its t_rk kPre steps ahead into a ring of
+// registers, so the L2 latency of T is off the chain of steps.
 template <bool UPPER>
 __global__ void __launch_bounds__(1024) k_trsm(const double2 *T, int64_t ldt, int nb, double2 *X,
                                                int64_t ldx) {
+  constexpr int kPre = 8;
   __shared__ double2 xs[1024];
   const int r = threadIdx.x;
+  // Every thread issues exactly one load per step (threads past nb and steps
+  // that take no term read an entry inside the triangle's nb x nb block), so
+  // the outstanding-load count is the same on every path and the compiler
+  // waits for the one load each step needs rather than for all of them.
+  const int rr = r < nb ? r : nb - 1;
+  const double2 *trow = T + rr;  // t_rk at trow[k * ldt]
   double2 *x = X + (int64_t)blockIdx.x * ldx;
-  Z xr = r < nb ? ld(x + r) : Z{0.0, 0.0};
-  if constexpr (!UPPER) {
-    for (int k = 0; k < nb - 1; ++k) {
-      if (r == k) xs[k] = make_double2(xr.re, xr.im);
-      __syncthreads();
-      if (r > k && r < nb) {
-        const double2 v = xs[k];
-        xr = zsub(xr, zmul(ld(T + r + (int64_t)k * ldt), Z{v.x, v.y}));
-      }
-    }
-  } else {
-    for (int k = nb - 1; k >= 0; --k) {
-      if (r == k) {
-        xr = zdiv(xr, ld(T + r + (int64_t)r * ldt));
-        xs[k] = make_double2(xr.re, xr.im);
-      }
-      __syncthreads();
-      if (r < k) {
-        const double2 v = xs[k];
-        xr = zsub(xr, zmul(ld(T + r + (int64_t)k * ldt), Z{v.x, v.y}));
+  Z xr = ld(x + rr);
+  if (r >= nb) xr = Z{0.0, 0.0};
+  const int steps = UPPER ? nb : nb - 1;
+  auto col = [&](int s) { return UPPER ? nb - 1 - s : s; };
+  if (steps > 0) {
+    const Z diag = UPPER ? ld(trow + (int64_t)rr * ldt) : Z{1.0, 0.0};
+    Z ring[kPre];
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) ring[j] = ld(trow + (int64_t)col(j < steps ? j : steps - 1) * ldt);
+    // steps past the last one (up to a multiple of kPre) take no term and
+    // write nothing; they keep every group of kPre steps alike
+    for (int s0 = 0; s0 < steps; s0 += kPre) {
+#pragma unroll
+      for (int j = 0; j < kPre; ++j) {
+        const int s = s0 + j;
+        const int k = col(s);
+        const bool live = s < steps;
+        if (live && r == k) {
+          if constexpr (UPPER) xr = zdiv(xr, diag);
+          xs[k] = make_double2(xr.re, xr.im);
+        }
+        lds_barrier();
+        if (live && r < nb && (UPPER ? r < k : r > k)) {
+          const double2 v = xs[k];
+          xr = zsub(xr, zmul(ring[j], Z{v.x, v.y}));
+        }
+        // the slot's next load goes out once its value is used, straight
+        // into the same registers
+        const int sn = s + kPre < steps ? s + kPre : steps - 1;
+        ring[j] = ld(trow + (int64_t)col(sn) * ldt);
       }
     }
   }
