@@ -171,9 +171,9 @@ __global__ void __launch_bounds__(256) k_panel_mult(double2 *A, int64_t lda, int
 // no earlier interchange named it, else E of the latest one that did (a chain
 // of decreasing t, resolved by pointer jumping). Row x >= c0 + t holds, just
 // before interchange t, E(t') for the latest t' < t with ipiv[c0 + t'] = x, or
-// x itself if there is none. One workgroup of 1024 threads, thread t for
-// interchange t, each scanning the w pivots in LDS. An entry outside [c, n)
-// counts as no interchange.
+// x itself if there is none. One workgroup of w threads rounded up to a
+// wave, thread t for interchange t, each scanning the w pivots in LDS. An
+// entry outside [c, n) counts as no interchange.
 __global__ void __launch_bounds__(1024) k_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1,
                                                      int64_t n, int64_t *dst, int64_t *src) {
   __shared__ int64_t piv[1024];
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(1024) k_swap_pairs(const int64_t *ipiv, int64_
   }
   nxt[t] = named_by >= 0 ? named_by : t;
   __syncthreads();
-  for (int r = 0; r < 10; ++r) {  // chains are shorter than 1024 = 2^10
+  for (int r = 1; r < w; r <<= 1) {  // a chain has fewer than w links
     const int v = nxt[nxt[t]];
     __syncthreads();
     nxt[t] = v;
@@ -350,7 +350,8 @@ hipError_t launch_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1, int64_
                              int64_t *pairs, hipStream_t st) {
   if (c1 <= c0) return hipSuccess;
   if (c1 - c0 > kLuMaxBlock) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3(1024), 0, st, ipiv, c0, c1, n, pairs,
+  hipLaunchKernelGGL(k_swap_pairs, dim3(1), dim3((unsigned)((c1 - c0 + 63) / 64 * 64)), 0, st, ipiv,
+                     c0, c1, n, pairs,
                      pairs + 2 * kLuMaxBlock);
   return hipGetLastError();
 }
