@@ -149,3 +149,21 @@ def test_nan_entry_is_the_pivot_like_the_model():
     _, ipiv_ref, singular = lu.zgetrf(A, nb, lu.update_model("t7", 6))
     assert singular
     assert np.array_equal(ipiv.cpu().numpy(), ipiv_ref)
+
+
+def test_lu_taller_than_one_pivot_batch():
+    # more than 2048 rows below the diagonal (the pivot workgroup's second
+    # batch of rows) for the first columns: factors and pivots bit-exact
+    n, nb = 2100, 64
+    A = _matrix(n, 1770)
+    assert oz.ozaki_set_split("t7") == 0
+    Ad, lda = dev(A)
+    ipiv = torch.zeros(n, dtype=torch.int64, device="cuda")
+    _say("lu tall", n, nb)
+    rc = oz.ozaki_zgetrf(n, Ad, lda, ipiv, nb, 3)
+    assert rc == 0, oz.ozaki_status_string(rc)
+    LU = host(Ad, n, n)
+    LU_ref, ipiv_ref, singular = lu.zgetrf(A, nb, lu.update_model("t7", 3))
+    assert not singular
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_ref)
+    assert bits_equal(LU, LU_ref), mismatch_report(LU, LU_ref)
