@@ -1490,6 +1490,7 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
     const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
     for (int64_t c = j0; c < j1; ++c)
       if ((rc = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return rc;
+    if ((rc = hip_rc(launch_lu_scale(a, lda, n, j0, j1, st)))) return rc;
     if ((rc = hip_rc(launch_swap_pairs(ipiv, j0, j1, n, pairs, st)))) return rc;
     if ((rc = hip_rc(launch_apply_pairs(a, lda, w, pairs, 0, j0, j1, n, st)))) return rc;
     if (j1 < n) {

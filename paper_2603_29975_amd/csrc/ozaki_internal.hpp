@@ -203,7 +203,8 @@ struct CrtArgs {
 hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
 
 // Blocked LU and inverse (see ozaki_lu.hip): one pivot column (pivot search,
-// swap over the panel columns [p0, p1), multipliers and panel update); the
+// swap over the panel columns [p0, p1) and panel update), the panel's
+// multipliers once its columns are done; the
 // row interchanges ipiv[c0..c1) (c1 - c0 <= kLuMaxBlock) turned into
 // destination/source row slots in `pairs` (kLuPairWords int64: destinations,
 // then sources, at offset 2 * kLuMaxBlock) and applied to the columns
@@ -212,6 +213,7 @@ hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
 constexpr int64_t kLuMaxBlock = 1024;  // panel / block width limit (one thread per block row)
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st);
+hipError_t launch_lu_scale(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, hipStream_t st);
 constexpr int64_t kLuPairWords = 4 * kLuMaxBlock;
 hipError_t launch_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1, int64_t n,
                              int64_t *pairs, hipStream_t st);

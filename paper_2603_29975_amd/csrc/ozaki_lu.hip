@@ -45,15 +45,14 @@ __device__ __forceinline__ bool beats(double v, int64_t i, double bv, int64_t bi
 }
 
 // Pivot of column c (rows c..n-1), then the swap of rows c and the pivot row
-// over the panel columns [p0, p1). One workgroup of 256 threads. When c > p0
-// the workgroup also stores the multipliers of column c - 1
-// (l_i = a_i,c-1 / a_c-1,c-1 for i >= c), which the panel update of that
-// column has finished using. Rows go in batches of 8 per thread, the loads of
-// both columns first so their latencies overlap; the waves reduce with
-// cross-lane shuffles and every thread reduces the 4 wave results itself.
-// The reduction's barrier orders the multiplier stores before the swap reads
-// them. A pivot that is zero or NaN is recorded in *singular (the smallest
-// such column).
+// over the panel columns [p0, p1). One workgroup of 256 threads, rows in
+// batches of 8 per thread with their loads in flight together; the waves
+// reduce with cross-lane shuffles and every thread reduces the 4 wave results
+// itself. A pivot that is zero or NaN is recorded in *singular (the smallest
+// such column). The panel's columns keep their unscaled entries below the
+// diagonal until k_panel_scale turns them into multipliers at the end of the
+// panel (column c is not updated after step c, only its rows exchanged, so
+// the multipliers come out the same).
 __global__ void __launch_bounds__(256) k_pivot_swap(double2 *A, int64_t lda, int64_t n, int64_t c,
                                                     int64_t p0, int64_t p1, int64_t *ipiv,
                                                     int64_t *singular) {
@@ -61,26 +60,19 @@ __global__ void __launch_bounds__(256) k_pivot_swap(double2 *A, int64_t lda, int
   __shared__ double sv[4];
   __shared__ int64_t si[4];
   const int t = threadIdx.x;
-  const bool mult = c > p0;
-  const int64_t q = c - 1;
-  const Z dq = mult ? ld(A + q + q * lda) : Z{1.0, 0.0};
   double best = -1.0;
   int64_t bi = n;
   for (int64_t i0 = c + t; i0 < n; i0 += 256 * kB) {
-    Z v[kB], m[kB];
+    Z v[kB];
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const int64_t i = i0 + 256 * j;
-      if (i < n) {
-        v[j] = ld(A + i + c * lda);
-        if (mult) m[j] = ld(A + i + q * lda);
-      }
+      if (i < n) v[j] = ld(A + i + c * lda);
     }
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const int64_t i = i0 + 256 * j;
       if (i < n) {
-        if (mult) st(A + i + q * lda, zdiv(m[j], dq));
         const double a = cabs1(v[j]);
         if (beats(a, i, best, bi)) {  // rows of a thread in increasing order
           best = a;
@@ -143,9 +135,7 @@ __global__ void __launch_bounds__(256) k_pivot_swap(double2 *A, int64_t lda, int
 
 // Panel update after the pivot of column c: a_ik -= (a_ic / a_cc) a_ck for
 // rows i > c and panel columns c < k < p1, one thread per element (each
-// recomputes its row's multiplier). The multipliers l_i = a_ic / a_cc are
-// stored afterwards: by the next column's pivot workgroup, or by k_panel_mult
-// for the last column of the panel.
+// computes its row's multiplier from the unscaled a_ic).
 __global__ void __launch_bounds__(256) k_panel_update(double2 *A, int64_t lda, int64_t n, int64_t c) {
   const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t k = c + 1 + blockIdx.y;
@@ -154,9 +144,12 @@ __global__ void __launch_bounds__(256) k_panel_update(double2 *A, int64_t lda, i
   st(A + i + k * lda, zsub(ld(A + i + k * lda), zmul(l, ld(A + c + k * lda))));
 }
 
-__global__ void __launch_bounds__(256) k_panel_mult(double2 *A, int64_t lda, int64_t n, int64_t c) {
-  const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+// End of the panel [p0, p1): the multipliers l_ic = a_ic / a_cc of every
+// panel column c, rows i > c, in place (one thread per entry).
+__global__ void __launch_bounds__(256) k_panel_scale(double2 *A, int64_t lda, int64_t n, int64_t p0) {
+  const int64_t c = p0 + blockIdx.y;
+  const int64_t i = p0 + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i <= c || i >= n) return;
   st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
 }
 
@@ -336,13 +329,16 @@ hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t st) {
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st) {
   hipLaunchKernelGGL(k_pivot_swap, dim3(1), dim3(256), 0, st, A, lda, n, c, p0, p1, ipiv, singular);
-  if (c + 1 < n) {
-    if (c + 1 < p1)
-      hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1), (unsigned)(p1 - c - 1)), dim3(256), 0,
-                         st, A, lda, n, c);
-    else
-      hipLaunchKernelGGL(k_panel_mult, dim3(blocks(n - c - 1)), dim3(256), 0, st, A, lda, n, c);
-  }
+  if (c + 1 < n && c + 1 < p1)
+    hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1), (unsigned)(p1 - c - 1)), dim3(256), 0, st,
+                       A, lda, n, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_lu_scale(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, hipStream_t st) {
+  if (p0 + 1 >= n || p1 <= p0) return hipSuccess;
+  hipLaunchKernelGGL(k_panel_scale, dim3(blocks(n - p0 - 1), (unsigned)(p1 - p0)), dim3(256), 0, st, A,
+                     lda, n, p0);
   return hipGetLastError();
 }
 
