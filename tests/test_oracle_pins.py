@@ -393,6 +393,59 @@ def test_alpha_beta_exact_cases():
     assert np.array_equal(got.real, -refz.imag) and np.array_equal(got.imag, refz.real)
 
 
+def _gauss_int(rng, shape, lo=-60, hi=60):
+    return rng.integers(lo, hi, shape).astype(float) + 1j * rng.integers(lo, hi, shape).astype(float)
+
+
+def _exact_complex_axpby(alpha, P, beta, C):
+    """alpha P + beta C on Gaussian integers with Python ints (no rounding):
+    (ar + ai i)(pr + pi i) = (ar pr - ai pi) + (ar pi + ai pr) i."""
+    out = np.empty(P.shape, dtype=np.complex128)
+    ar, ai = int(alpha.real), int(alpha.imag)
+    br, bi = int(beta.real), int(beta.imag)
+    for idx in np.ndindex(P.shape):
+        pr, pi = int(P[idx].real), int(P[idx].imag)
+        cr, ci = (int(C[idx].real), int(C[idx].imag)) if C is not None else (0, 0)
+        re = ar * pr - ai * pi + br * cr - bi * ci
+        im = ar * pi + ai * pr + br * ci + bi * cr
+        out[idx] = complex(re, im)
+    return out
+
+
+def test_complex_alpha_beta_against_gaussian_integers():
+    """Reference-BLAS C <- alpha op(A) op(B) + beta C with complex alpha and
+    beta (reading R5), on Gaussian-integer data where every rounding is exact:
+    the model must equal the exact result computed with Python integers. A
+    conjugated or dropped imaginary part of beta or alpha changes the answer."""
+    rng = np.random.default_rng(52)
+    A, B, C = _gauss_int(rng, (5, 7)), _gauss_int(rng, (7, 4)), _gauss_int(rng, (5, 4))
+    P = np.empty((5, 4), dtype=np.complex128)
+    for i in range(5):
+        for j in range(4):
+            re = sum(int(A[i, l].real) * int(B[l, j].real) - int(A[i, l].imag) * int(B[l, j].imag)
+                     for l in range(7))
+            im = sum(int(A[i, l].real) * int(B[l, j].imag) + int(A[i, l].imag) * int(B[l, j].real)
+                     for l in range(7))
+            P[i, j] = complex(re, im)
+    from oracle import ozaki_b8
+    for alpha, beta in ((2 - 3j, -1 + 2j), (-1j, 3 + 1j), (1 + 0j, 2j), (-2 + 0j, -4 - 1j)):
+        want = _exact_complex_axpby(alpha, P, beta, C)
+        for model in (lambda a, b: ozaki.ozaki_gemm("N", "N", A, B, 3, a, b, C),
+                      lambda a, b: ozaki_b8.ozaki_gemm_b8("N", "N", A, B, 3, a, b, C)):
+            got = model(alpha, beta)
+            assert np.array_equal(got, want), (alpha, beta)
+    # beta-only paths (alpha = 0, or k = 0): C <- beta C
+    for beta in (-1 + 2j, 2 - 5j, 1j):
+        want = _exact_complex_axpby(0j, np.zeros_like(C), beta, C)
+        assert np.array_equal(ozaki.ozaki_gemm("N", "N", A, B, 3, 0.0, beta, C), want)
+        assert np.array_equal(ozaki.ozaki_gemm("N", "N", A[:, :0], B[:0], 3, 1 + 1j, beta, C),
+                              want)
+        assert np.array_equal(ozaki.scale_only(beta, C, C.shape, True), want)
+    # the epilogue on its own, against the exact result
+    assert np.array_equal(ozaki.apply_alpha_beta(P, 2 - 3j, -1 + 2j, C),
+                          _exact_complex_axpby(2 - 3j, P, -1 + 2j, C))
+
+
 def test_nonfinite_rows_and_columns_become_nan():
     A, B = uniform_binade(6, 5, 7, seed=51)
     A2 = A.copy()
