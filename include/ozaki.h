@@ -294,6 +294,16 @@ int ozaki_batched_cache_clear(void);
  *   device's architecture name and ignores them otherwise.
  * The table is process-wide and not thread-safe.
  */
+/*
+ * Cap on the number of workgroups of the persistent slice GEMM (single and
+ * batched products; 0, the default, launches one grid sized to the CU
+ * count). With a cap below the tile count every workgroup walks several
+ * output tiles in turn, reusing its int64 carry space; results are
+ * bit-identical for every cap. For tests of that reuse at small sizes and for
+ * leaving CUs to concurrent work. Errors: -1 for a negative cap.
+ */
+int ozaki_set_grid_limit(int64_t max_workgroups);
+
 int ozaki_autotune(char kind, int64_t m, int64_t n, int64_t k, int slices, int reps, int *best,
                    double *best_ms);
 int ozaki_tune_set(char kind, int64_t m, int64_t n, int64_t k, int slices, int id);

@@ -31,7 +31,7 @@ __all__ = [
     "ozaki_tune_configs", "ozaki_tune_save", "ozaki_tune_load", "ozaki_tune_clear",
     "ozaki2_dgemm", "ozaki2_zgemm", "ozaki2_moduli", "ozaki2_beta_bits", "ozaki2_workspace_bytes",
     "MODULI_MIN", "MODULI_MAX", "K2_MAX", "ozaki_set_split", "ozaki_get_split", "SPLIT_TRUNC7",
-    "SPLIT_BAL8", "S8_MAX", "ozaki_zgetrf", "ozaki_zgetri",
+    "SPLIT_BAL8", "S8_MAX", "ozaki_zgetrf", "ozaki_zgetri", "ozaki_set_grid_limit",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -71,6 +71,7 @@ _SIG = {
                                 _i64, ozaki_z, _vp, _i64, _c.c_int]),
     "ozaki2_moduli": (_c.c_int, [_c.c_int, _vp]),
     "ozaki_set_split": (_c.c_int, [_c.c_int]),
+    "ozaki_set_grid_limit": (_c.c_int, [_i64]),
     "ozaki_zgetrf": (_c.c_int, [_i64, _vp, _i64, _vp, _i64, _c.c_int]),
     "ozaki_zgetri": (_c.c_int, [_i64, _vp, _i64, _vp, _vp, _i64, _i64, _c.c_int]),
     "ozaki_get_split": (_c.c_int, []),
@@ -210,6 +211,11 @@ def ozaki_zgetri(n, LU, lda, ipiv, X, ldx, nb, slices) -> int:
 
 def ozaki_get_split() -> int:
     return library().ozaki_get_split()
+
+
+def ozaki_set_grid_limit(max_workgroups) -> int:
+    """Cap the persistent slice GEMM's workgroup count (0: no cap)."""
+    return library().ozaki_set_grid_limit(int(max_workgroups))
 
 
 def ozaki2_moduli(moduli):

@@ -42,6 +42,7 @@ struct State {
   int split = -1;  // OZAKI_SPLIT_* of the single-product calls (-1: not read from OZAKI_SPLIT yet)
   void *user_ws = nullptr;
   size_t user_ws_bytes = 0;
+  int64_t grid_limit = 0;  // ozaki_set_grid_limit (0: one persistent grid per the CU count)
   void *own_ws[kMaxDev] = {};
   size_t own_ws_bytes[kMaxDev] = {};
   DevInfo dev[kMaxDev];
@@ -356,6 +357,7 @@ GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, dou
   a.flush_ws = reinterpret_cast<int64_t *>(ws + p.off_flush);
   a.kb_chunk = p.kb_chunk;
   a.chunked = p.nkb > p.kb_chunk ? 1 : 0;
+  a.max_groups = g.grid_limit;
   return a;
 }
 
@@ -729,6 +731,7 @@ int enqueue_plan(const BatchedPlan &pl, hipStream_t st, bool capturing) {
     a.flush_ws = reinterpret_cast<int64_t *>(base + pl.off_flush);
     a.kb_chunk = kb_chunk_for(gd.S);
     a.chunked = gd.chunked ? 1 : 0;
+    a.max_groups = g.grid_limit;
     if ((rc = hip_rc(launch_ozgemm_grouped(gd.S, pl.tune_id, a, g.dev[pl.dev].num_cu, st))))
       return rc;
   }
@@ -1852,6 +1855,12 @@ int ozaki_set_split(int mode) {
 }
 
 int ozaki_get_split(void) { return split_b8() ? OZAKI_SPLIT_BAL8 : OZAKI_SPLIT_TRUNC7; }
+
+int ozaki_set_grid_limit(int64_t max_workgroups) {
+  if (max_workgroups < 0) return -1;
+  g.grid_limit = max_workgroups;
+  return OZAKI_OK;
+}
 
 int ozaki_timing_enable(int on) {
   g_tm.on = on != 0;

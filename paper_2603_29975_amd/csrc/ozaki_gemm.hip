@@ -213,7 +213,8 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
   // persistent grid: 8 waves per CU, i.e. one workgroup of 8 waves or two of 4
   // (whose barriers are independent, so one's MFMAs fill the other's waits)
   const int64_t per_cu = C_::NW >= 8 ? 1 : 8 / C_::NW;
-  const int64_t grid = std::min<int64_t>(ntiles, per_cu * num_cu);
+  int64_t grid = std::min<int64_t>(ntiles, per_cu * num_cu);
+  if (a.max_groups > 0) grid = std::min<int64_t>(grid, a.max_groups);
   if (grid <= 0) return hipSuccess;
   const dim3 g((unsigned)grid), b(C_::NT);
   if (grouped) {

@@ -87,6 +87,7 @@ struct GemmArgs {
   int64_t kb_chunk;   // contraction blocks per exact INT32 chunk
   int chunked;        // some problem has nkb > kb_chunk
   int order;          // tile order (set from the tuning id at launch)
+  int64_t max_groups; // cap on the persistent grid (0: no cap beyond the CU count)
 };
 
 // Tile counts of a problem for a configuration (host side).

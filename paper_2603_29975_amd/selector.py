@@ -26,6 +26,7 @@ from . import (MLP_PARAMS, OzakiError, ozaki_features, ozaki_mlp_adam, ozaki_mlp
 
 S_LO = 3
 S_HI = 12
+KAPPA = 8.0      # probe safety factor used when the weights file stores none
 
 
 def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32):
@@ -311,9 +312,16 @@ def save(path, theta, margin, target, meta):
              target=np.float64(target), **{k: np.asarray(v) for k, v in meta.items()})
 
 
-def load(path):
+def load(path, with_meta=False):
+    """(theta, margin, target) of a saved selector, plus the dict of its other
+    stored values when with_meta is set."""
     z = np.load(path, allow_pickle=False)
-    return z["theta"], float(z["margin"]), float(z["target"])
+    out = (z["theta"], float(z["margin"]), float(z["target"]))
+    if with_meta:
+        meta = {key: (z[key].item() if z[key].ndim == 0 else z[key]) for key in z.files
+                if key not in ("theta", "margin", "target")}
+        return out + (meta,)
+    return out
 
 
 def evaluate_gain(theta, margin, target, kappa=8.0, pairs=None, steps=5, log=None):

@@ -603,3 +603,27 @@ def test_bf16_rounding_and_adam_first_step():
     g = np.array([0.5, -2.0, 0.0, 1e-3])
     th, m, v = sel.adam(np.zeros(4), np.zeros(4), np.zeros(4), g, 0.01, 0.9, 0.999, 1e-8, 1)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_sampled_reference_equals_full_dd_on_its_entries():
+    """The sampled accuracy check (4096-entry + whole rows/columns form used at
+    16384^3) against the full double-double product and the plain definition
+    of the denominators, on a product small enough for both."""
+    from oracle.sampled import SampledReference, sample_entries
+    A, B = scaled_gaussian(40, 36, 50, seed=60, rmax=10)
+    ref = SampledReference(A, B, nrand=100, nrows=3, ncols=2, seed=61)
+    ri, cj, rows, cols = sample_entries(40, 36, 100, 3, 2, 61)
+    assert np.array_equal(ri, ref.ri) and np.array_equal(cj, ref.cj)
+    assert 39 in rows and 35 in cols and rows.size == 3 and cols.size == 2
+    assert ri.size == 100 + 3 * 36 + 2 * 40
+    hi, lo = dd.dd_gemm("N", "N", A, B)
+    assert np.array_equal(ref.hi, hi[ri, cj]) and np.array_equal(ref.lo, lo[ri, cj])
+    den = metrics.abs_product("N", "N", A, B)[ri, cj]
+    assert np.allclose(ref.den, den, rtol=1e-13, atol=0)
+    C = ozaki.ozaki_gemm("N", "N", A, B, 4)
+    full = metrics.err_comp(C, hi, lo, metrics.abs_product("N", "N", A, B))
+    assert ref.err_comp(C[ri, cj]) <= full
+    # every row asked for: the whole matrix
+    ri2, cj2, rows2, _ = sample_entries(40, 36, 0, 40, 0, 1)
+    assert rows2.size == 40 and ri2.size == 40 * 36
+    assert ref.err_comp(C[ri, cj]) == metrics.err_comp(C[ri, cj], hi[ri, cj], lo[ri, cj], den)

@@ -23,6 +23,7 @@ __all__ = [
     "uniform_binade",
     "kkr_operands",
     "scaled_gaussian",
+    "illcond_operands",
     "batched_problems",
     "complex_normal",
 ]
@@ -102,6 +103,50 @@ def scaled_gaussian(m: int, n: int, k: int, seed: int, rmax: int = 30, complex_:
     rb = rng.integers(-rmax, rmax + 1, size=n)
     A = A * np.ldexp(1.0, ra)[:, None]
     B = B * np.ldexp(1.0, rb)[None, :]
+    return A, B
+
+
+def _blocked_complex_normal(seq: np.random.SeedSequence, rows: int, cols: int,
+                            nblocks: int) -> np.ndarray:
+    """rows x cols circular complex Gaussian (E|z|^2 = 1), drawn in `nblocks`
+    row blocks, each from its own child stream of `seq` (so the bytes do not
+    depend on how many threads draw them). Real and imaginary parts are
+    interleaved draws of one standard normal stream per block."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty((rows, cols, 2), dtype=np.float64)
+    bounds = np.linspace(0, rows, nblocks + 1).astype(np.int64)
+    children = seq.spawn(nblocks)
+
+    def fill(b):
+        r0, r1 = int(bounds[b]), int(bounds[b + 1])
+        if r1 > r0:
+            g = np.random.default_rng(children[b])
+            g.standard_normal(out=out[r0:r1])
+            out[r0:r1] *= np.sqrt(0.5)
+
+    with ThreadPoolExecutor(max_workers=min(nblocks, 16)) as ex:
+        list(ex.map(fill, range(nblocks)))
+    return out.view(np.complex128).reshape(rows, cols)
+
+
+def illcond_operands(m: int, n: int, k: int, seed: int, rmax: int = 30, nblocks: int = 64):
+    """Large ill-conditioned complex operands: complex Gaussian A (m x k) and
+    B (k x n) with every row of A and every column of B scaled by 2^r,
+    r ~ uniform integer in [-rmax, rmax] (exact in FP64).
+
+    The same family as ``scaled_gaussian``, drawn block-parallel so that the
+    16384^3 case takes seconds: child streams of SeedSequence(seed) give A's
+    row blocks, B's row blocks and the exponents r, in that order.
+    """
+    seq = np.random.SeedSequence(seed)
+    sa, sb, sr = seq.spawn(3)
+    A = _blocked_complex_normal(sa, m, k, nblocks)
+    B = _blocked_complex_normal(sb, k, n, nblocks)
+    g = np.random.default_rng(sr)
+    ra = g.integers(-rmax, rmax + 1, size=m)
+    rb = g.integers(-rmax, rmax + 1, size=n)
+    A *= np.ldexp(1.0, ra)[:, None]
+    B *= np.ldexp(1.0, rb)[None, :]
     return A, B
 
 
