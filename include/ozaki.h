@@ -356,7 +356,12 @@ int ozaki_features(char kind, char transa, char transb, int64_t m, int64_t n, in
  * parameters at byte 0, Adam first and second moments and the gradient after
  * them (OZAKI_MLP_PARAMS floats each, in that order), then BF16 copies.
  * `scratch` is a device buffer of ozaki_mlp_scratch_bytes(batch) bytes; the
- * backward pass reads the activations the forward pass left there.
+ * backward pass reads the activations the forward pass left there. Its
+ * layout (bp = batch rounded up to a multiple of 32; regions in this order,
+ * each starting at a multiple of 256 bytes; rows >= batch are zero): Xh
+ * (bp x 64 BF16, row-major), Xh^T, H1 (bp x 128 FP32, after the ReLU), H1h
+ * (BF16), H1h^T, H2 (FP32), H2h, H2h^T, then after a backward pass dH2h
+ * (bp x 128 BF16), dH2h^T, dH1h (BF16), dH1h^T.
  *   init      He-uniform weights from SplitMix64(seed + index), zero biases
  *   refresh   rebuild the BF16 copies after writing parameters directly
  *   forward   y[b] for b < batch from X[b][64] (device, FP32)

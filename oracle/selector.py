@@ -115,15 +115,16 @@ def loss(y, t, under):
     return float(np.mean(w * e * e))
 
 
-def backward(theta, X, t, under, quantize=True):
+def backward_stages(y, c, t, under, quantize=True):
+    """The backward pass from the forward values y and c (X16, H1, H1h, H2,
+    W2h, w3h as forward() returns them): the gradient (packed like theta) and
+    the intermediates dy, dH2h, dH1h."""
     q = bf16 if quantize else (lambda v: np.asarray(v, dtype=np.float64))
-    y, c = forward(theta, X, quantize)
-    B = X.shape[0]
+    B = y.shape[0]
     e = y - t
     w = np.where(y < t, under, 1.0)
     dy = 2.0 * w * e / B
     dH2h = q(dy[:, None] * c["w3h"][None, :] * (c["H2"] > 0))
-    g = {"W3": None}
     gw3 = dy @ c["H2"]
     gb3 = np.array([dy.sum()])
     gW2 = dH2h.T @ c["H1h"]
@@ -131,8 +132,14 @@ def backward(theta, X, t, under, quantize=True):
     dH1h = q((dH2h @ c["W2h"]) * (c["H1"] > 0))
     gW1 = dH1h.T @ c["X16"]
     gb1 = dH1h.sum(axis=0)
-    del g
-    return pack({"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "w3": gw3, "b3": gb3}), loss(y, t, under)
+    g = pack({"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "w3": gw3, "b3": gb3})
+    return g, dict(dy=dy, dH2h=dH2h, dH1h=dH1h)
+
+
+def backward(theta, X, t, under, quantize=True):
+    y, c = forward(theta, X, quantize)
+    g, _ = backward_stages(y, c, t, under, quantize)
+    return g, loss(y, t, under)
 
 
 def adam(theta, m, v, grad, lr, b1, b2, eps, step):
