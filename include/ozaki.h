@@ -141,7 +141,8 @@ int ozaki_get_split(void);
  * Argument numbers as ozaki_dgemm, with moduli 14 (OZAKI2_MODULI_MIN ..
  * OZAKI2_MODULI_MAX, and -14 also when beta < 1: too few moduli for K').
  * K' above OZAKI2_K_MAX (exact INT32 sums) returns -5. The workspace holds
- * the residue planes and the INT32 products: see ozaki2_workspace_bytes.
+ * the residue planes (see ozaki2_workspace_bytes); the modular products and
+ * the rebuild run in one fused kernel and never leave the chip.
  */
 #define OZAKI2_MODULI_MIN 2
 #define OZAKI2_MODULI_MAX 20
@@ -243,12 +244,17 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
  * Selector for the automatic mode of ozaki_zgemm_batched (slices == NULL):
  * params are the OZAKI_MLP_PARAMS FP32 MLP parameters (host array, copied).
  * A problem gets s = ceil(prediction + margin) slices (clamped to 1..12); its
- * product is formed with alpha = 1, beta = 0 in library memory and probed
- * (ozaki_probe, 2 vectors); while max_i est[i] * kappa > target and s < 12,
- * s rises by one and the product is redone. C is then finished with alpha and
- * beta by the fused epilogue's formula, so the result equals ozaki_zgemm at the
- * final s bit for bit. The automatic mode synchronises the stream (the slice
- * counts are decided on the host) and is not captured into graphs.
+ * product is formed in library memory (alpha = 1, beta = 0, before the
+ * 2^(e_i + f_j) scaling) with its operands split to s + 1 slices, then probed
+ * (ozaki_probe's estimate, 2 vectors, seed 0x5eed0000 + round). If
+ * max_i est[i] * kappa > target, the next diagonal is added to the stored sums
+ * on the device (with trunc-7 slices this is exactly the product at s + 1) and
+ * the probe runs again; a product still over the target is formed again at
+ * s + 2 in a further pass, and so on up to s = 12. C is then finished with
+ * alpha and beta by the fused epilogue's formula, so the result equals
+ * ozaki_zgemm at the final s bit for bit. The automatic mode synchronises the
+ * stream twice per pass (the predictions, then the pass's final slice counts)
+ * and is not captured into graphs.
  * Errors: params -1, margin -2 (outside [-4, 8]), target -3 (<= 0), kappa -4 (< 1).
  */
 int ozaki_load_selector(const float *params, float margin, double target, double kappa);
@@ -263,8 +269,10 @@ int ozaki_batched_cache_clear(void);
  * Tile autotuner of the fused slice GEMM. The paper takes its emulation
  * library as shipped (Section 3.1); the tile candidates and the tuning table
  * are this library's own.
- * A tuning id is 2 * tile configuration + tile order; ozaki_tune_configs()
- * gives their number. Every id computes bit-identical results: only the
+ * A tuning id below 14 is 2 * tile configuration + tile order (0: down the
+ * output rows, 1: along the columns); ids 14 .. 20 are configurations 0 .. 6
+ * walking the tiles in groups of 16 tile rows. ozaki_tune_configs() gives
+ * their number. Every id computes bit-identical results: only the
  * workgroup shape, the LDS ring depth and the order in which the persistent
  * workgroups walk the output tiles differ.
  * The table maps (kind, slices, bucket of m, of n' = n or 2n, of the 32-deep
@@ -415,8 +423,7 @@ int ozaki_timing_enable(int on);
 int ozaki_timing_read(double *ms, int64_t *calls);
 
 /* Release the library's own device buffers: the workspace, the scratch of
- * the automatic slice mode and the Ozaki-II library-GEMM handles (safe to
- * call more than once). */
+ * the automatic slice mode and the LU flags (safe to call more than once). */
 int ozaki_finalize(void);
 
 /* Static text for a status code. */

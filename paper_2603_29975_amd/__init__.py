@@ -130,6 +130,14 @@ def library():
             raise OzakiUnavailable(
                 f"{library_path} is missing: build it with `python paper_2603_29975_amd/build.py` "
                 "(or __graft_entry__.build()); there is no fallback implementation")
+        # PyTorch first: its HIP runtime must be the process's one before the
+        # library's dependency on libamdhip64 is resolved (loading the library
+        # first pulls in another copy, and device calls made through the two
+        # then disagree about the device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(library_path)
         for name, (res, args) in _SIG.items():
             fn = getattr(lib, name)

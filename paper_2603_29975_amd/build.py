@@ -3,7 +3,7 @@
 Every source under csrc/ is compiled for gfx950 only, with FP contraction off
 (the recombination and alpha/beta epilogues must round every operation on its
 own) and packed-FP32 instruction selection disabled. The objects are linked into
-paper_2603_29975_amd/libozaki.so next to this file, against rocBLAS.
+paper_2603_29975_amd/libozaki.so next to this file.
 """
 from __future__ import annotations
 
@@ -23,9 +23,6 @@ BLAS_LIB = os.path.join(HERE, "libozaki_blas.so")  # Fortran DGEMM/ZGEMM interpo
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# rocBLAS (the Ozaki-II path's batched INT8 GEMM); resolved at load time by
-# soname, so a process that already holds a librocblas.so.5 (PyTorch's) uses it.
-ROCM_LIB = os.environ.get("ROCM_LIB", "/opt/rocm/lib")
 
 CFLAGS = [
     f"--offload-arch={ARCH}",
@@ -60,8 +57,7 @@ def build(verbose: bool = False, extra=()) -> str:
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), srcs))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs,
-           f"-L{ROCM_LIB}", "-lrocblas"]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     # host-only interposer, linked against libozaki.so next to it

@@ -20,8 +20,6 @@
 #include <map>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "../../include/ozaki.h"
 #include "ozaki_internal.hpp"
 
@@ -431,35 +429,18 @@ int native_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64
 }
 
 // ---------------------------------------------------------------- Ozaki-II
-// The N modular products are one plain strided-batched INT8 x INT8 -> INT32
-// library GEMM (rocBLAS); the integer conversion, residues and the CRT
-// rebuild are this library's kernels. One rocBLAS handle per device, bound to
-// the library's stream at every call.
-rocblas_handle g_blas[kMaxDev] = {};
-
-int blas_handle(int dev, rocblas_handle *h) {
-  if (g_blas[dev] == nullptr && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success) {
-    g_blas[dev] = nullptr;
-    return OZAKI_ERR_INTERNAL;
-  }
-  if (rocblas_set_stream(g_blas[dev], g.stream) != rocblas_status_success) return OZAKI_ERR_INTERNAL;
-  *h = g_blas[dev];
-  return OZAKI_OK;
-}
-
-// Workspace of one Ozaki-II product: exponent codes, the residue planes of A'
-// (N x m rows) and B' (N x n' rows), K' padded to 128 bytes per row, and the N
-// INT32 product planes (m x n').
+// Workspace of one Ozaki-II product: exponent codes, then the residue planes
+// of A' (N planes of m rows) and of B' (N planes of n' rows) in the packed
+// fragment layout (rows padded to 128, K' to 128).
 struct Plan2 {
   int N, beta;
   bool cplx;
-  int64_t m, n, k, kprime, kpad, nprime;
-  size_t off_codeA, off_codeB, off_RA, off_RB, off_C, total;
+  int64_t m, n, k, kprime, kpad, nprime, nkb, nrbQ, nrbP;
+  size_t off_codeA, off_codeB, off_RA, off_RB, total;
 };
 
 // 0, or the negative argument number of a size the path cannot take: -5 for
-// K' above OZAKI2_K_MAX, -14 for too few moduli (beta < 1), -3/-4 for
-// dimensions beyond the library GEMM's 32-bit sizes.
+// K' above OZAKI2_K_MAX, -14 for too few moduli (beta < 1).
 int make_plan2(bool cplx, int64_t m, int64_t n, int64_t k, int N, Plan2 *p) {
   *p = Plan2{};
   p->N = N;
@@ -473,19 +454,18 @@ int make_plan2(bool cplx, int64_t m, int64_t n, int64_t k, int N, Plan2 *p) {
   p->beta = crt_beta(N, std::max<int64_t>(p->kprime, 1));
   if (p->beta < 1) return -14;
   p->kpad = round_up(std::max<int64_t>(p->kprime, 1), 128);
-  if (m > 0x7fffffffll) return -3;
-  if (p->nprime > 0x7fffffffll) return -4;
+  p->nkb = p->kpad / 32;
+  p->nrbQ = round_up(std::max<int64_t>(m, 1), kRowPad) / 32;
+  p->nrbP = round_up(std::max<int64_t>(p->nprime, 1), kRowPad) / 32;
   size_t off = 0;
   p->off_codeA = off;
   off += align256(sizeof(int) * (size_t)std::max<int64_t>(m, 1));
   p->off_codeB = off;
   off += align256(sizeof(int) * (size_t)std::max<int64_t>(n, 1));
   p->off_RA = off;
-  off += align256((size_t)N * m * p->kpad);
+  off += align256((size_t)N * p->nrbQ * p->nkb * kFragBytes);
   p->off_RB = off;
-  off += align256((size_t)N * p->nprime * p->kpad);
-  p->off_C = off;
-  off += align256(sizeof(int32_t) * (size_t)N * m * p->nprime);
+  off += align256((size_t)N * p->nrbP * p->nkb * kFragBytes);
   p->total = off;
   return 0;
 }
@@ -511,8 +491,6 @@ int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, 
   if ((rc = make_plan2(cplx, m, n, k, moduli, &p))) return rc;
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
-  rocblas_handle h = nullptr;
-  if ((rc = blas_handle(dev, &h))) return rc;
   void *wsv = nullptr;
   if ((rc = get_workspace(p.total, &wsv))) return rc;
   char *ws = static_cast<char *>(wsv);
@@ -520,7 +498,6 @@ int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, 
   int *codeB = reinterpret_cast<int *>(ws + p.off_codeB);
   int8_t *RA = reinterpret_cast<int8_t *>(ws + p.off_RA);
   int8_t *RB = reinterpret_cast<int8_t *>(ws + p.off_RB);
-  int32_t *Ci = reinterpret_cast<int32_t *>(ws + p.off_C);
   const View va = view_opA(A, transa, m, k, lda, cplx);
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
   hipStream_t st = g.stream;
@@ -534,44 +511,34 @@ int ozaki2_gemm_impl(bool cplx, char transa, char transb, int64_t m, int64_t n, 
   phase_end(mk, st);
 
   mk = phase_begin(OZAKI_PHASE_SPLIT, st);
-  const int64_t planeA = m * p.kpad, planeB = p.nprime * p.kpad;
-  if ((rc = hip_rc(launch_residues(va, cplx, false, codeA, moduli, p.beta, RA, p.kpad, planeA, st))))
+  if ((rc = hip_rc(launch_residues(va, cplx, false, codeA, moduli, p.beta, RA, p.nrbQ, p.nkb, st))))
     return rc;
-  if ((rc = hip_rc(launch_residues(vb, cplx, true, codeB, moduli, p.beta, RB, p.kpad, planeB, st))))
+  if ((rc = hip_rc(launch_residues(vb, cplx, true, codeB, moduli, p.beta, RB, p.nrbP, p.nkb, st))))
     return rc;
   phase_end(mk, st);
 
-  // C_k (m x n', column-major) = RA_k^T RB_k with RA_k, RB_k stored K'-major.
+  // the modular products and the rebuild: one fused kernel
   mk = phase_begin(OZAKI_PHASE_GEMM, st);
-  const int32_t one = 1, zero = 0;
-  const int64_t planeC = m * p.nprime;
-  const rocblas_status bs = rocblas_gemm_strided_batched_ex(
-      h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m,
-      (rocblas_int)p.nprime, (rocblas_int)p.kpad, &one, RA, rocblas_datatype_i8_r,
-      (rocblas_int)p.kpad, (rocblas_stride)planeA, RB, rocblas_datatype_i8_r, (rocblas_int)p.kpad,
-      (rocblas_stride)planeB, &zero, Ci, rocblas_datatype_i32_r, (rocblas_int)m,
-      (rocblas_stride)planeC, Ci, rocblas_datatype_i32_r, (rocblas_int)m, (rocblas_stride)planeC,
-      (rocblas_int)moduli, rocblas_datatype_i32_r, rocblas_gemm_algo_standard, 0, 0);
-  phase_end(mk, st);
-  if (bs != rocblas_status_success) return OZAKI_ERR_HIP;
-
-  mk = phase_begin(OZAKI_PHASE_RECON, st);
-  CrtArgs ca{};
-  ca.Cint = Ci;
-  ca.plane = planeC;
-  ca.m = m;
-  ca.n = n;
-  ca.codeA = codeA;
-  ca.codeB = codeB;
-  ca.beta = p.beta;
-  ca.ar = ar;
-  ca.ai = ai;
-  ca.br = br;
-  ca.bi = bi;
-  ca.beta_zero = beta_zero ? 1 : 0;
-  ca.C = C;
-  ca.ldc = ldc;
-  rc = hip_rc(launch_crt(moduli, cplx, ca, st));
+  Oz2Args ga{};
+  ga.RA = RA;
+  ga.RB = RB;
+  ga.nrbQ = p.nrbQ;
+  ga.nrbP = p.nrbP;
+  ga.nkb = p.nkb;
+  ga.m = m;
+  ga.nprime = p.nprime;
+  ga.codeA = codeA;
+  ga.codeB = codeB;
+  ga.beta = p.beta;
+  ga.ar = ar;
+  ga.ai = ai;
+  ga.br = br;
+  ga.bi = bi;
+  ga.beta_zero = beta_zero ? 1 : 0;
+  ga.cplx = cplx ? 1 : 0;
+  ga.C = C;
+  ga.ldc = ldc;
+  rc = hip_rc(launch_oz2gemm(moduli, ga, g.dev[dev].num_cu, st));
   phase_end(mk, st);
   if (g_tm.on) ++g_tm.calls;
   return rc;
@@ -768,7 +735,8 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
                const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
                const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
                const int *slices, int num_cu, BatchedPlan *pl, Alloc alloc,
-               std::vector<uint8_t> &host) {
+               std::vector<uint8_t> &host, const int *split_slices = nullptr,
+               bool unscaled = false) {
   pl->used.assign((size_t)batch, 0);
   pl->tune_id = batched_tune_id();
   std::vector<GemmProblem> probs;
@@ -789,7 +757,13 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
       if (!beta_one) pl->scales.push_back({m[b], n[b], ldc[b], beta[b].re, beta[b].im, beta_zero, C[b]});
       continue;
     }
-    const Plan p = make_plan(true, m[b], n[b], k[b], slices[b], num_cu);
+    // the operands are split to split_slices[b] >= slices[b] digits (trunc-7
+    // digits at s are a prefix of those at more slices); the GEMM takes the
+    // first slices[b]
+    const int S_split = split_slices != nullptr ? std::max(split_slices[b], slices[b]) : slices[b];
+    Plan p = make_plan(true, m[b], n[b], k[b], S_split, num_cu);
+    p.S = slices[b];
+    p.kb_chunk = kb_chunk_for(slices[b]);
     plans.push_back(p);
     prob_ws.push_back(ws_total);
     ws_total += align256(p.off_flush);  // codes and packed operands (carry space is shared)
@@ -797,13 +771,14 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
     if (p.nkb > p.kb_chunk) flush_bytes = std::max(flush_bytes, gemm_flush_bytes(p.S, 0, num_cu));
     GemmProblem gp = gemm_problem(p, nullptr, alpha[b].re, alpha[b].im, beta[b].re, beta[b].im,
                                   beta_zero, C[b], ldc[b], nullptr);
+    gp.unscaled = unscaled ? 1 : 0;
     probs.push_back(gp);
     const View va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
     const View vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
     scans.push_back({va, nullptr, 1, va.sr == 1 ? 1 : 0});
     scans.push_back({vb, nullptr, 1, vb.sr == 1 ? 1 : 0});
-    splits.push_back({va, nullptr, nullptr, p.nrbQ, p.nkb, p.S, 1, 0});
-    splits.push_back({vb, nullptr, nullptr, p.nrbP, p.nkb, p.S, 1, 1});
+    splits.push_back({va, nullptr, nullptr, p.nrbQ, p.nkb, S_split, 1, 0});
+    splits.push_back({vb, nullptr, nullptr, p.nrbP, p.nkb, S_split, 1, 1});
   }
   const size_t np = probs.size();
 
@@ -1083,10 +1058,21 @@ int auto_ws(size_t bytes, char **out) {
   return OZAKI_OK;
 }
 
-// Slices per problem from the selector, checked by the residual probe: each
-// product is formed with alpha = 1, beta = 0 in library memory, probed, and
-// redone one slice higher while its estimate misses the target; C is then
-// finished with alpha and beta exactly as the fused epilogue would.
+// Slices per problem from the selector, checked by the residual probe. Every
+// product is formed at its predicted s with its operands split one slice
+// deeper, into library memory as the recombined sums before the final
+// 2^(e_i + f_j) scaling (alpha = 1, beta = 0). The probe and the decision run
+// on the device: a product that misses the target gets its next diagonal
+// added to the stored sums (the trunc-7 prefix property: the result is then
+// exactly the product at s + 1) and is probed again. The host synchronises
+// twice per pass (the predictions, then the final slice counts); a product
+// still missing the target after that is formed again two slices higher in a
+// further pass. C is finished with alpha and beta exactly as the fused
+// epilogue would, so the result equals a fixed-s call at the final s bit for
+// bit.
+constexpr uint64_t kProbeSeed = 0x5eed0000ull;  // round r of the automatic mode probes with seed + r
+constexpr int kProbeVectors = 2;
+
 int auto_batched(const char *transa, const char *transb, const int64_t *m, const int64_t *n,
                  const int64_t *k, const ozaki_z *alpha, const ozaki_z *const *A,
                  const int64_t *lda, const ozaki_z *const *B, const int64_t *ldb,
@@ -1121,6 +1107,7 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     return o;
   };
   std::vector<size_t> o_codeA(ne), o_codeB(ne), o_P(ne), o_w(ne), o_est(ne);
+  int64_t diag_tiles_all = 0;
   for (int64_t e = 0; e < ne; ++e) {
     const int64_t b = E[e];
     o_codeA[e] = take(sizeof(int) * m[b]);
@@ -1128,6 +1115,7 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     o_P[e] = take(sizeof(ozaki_z) * m[b] * n[b]);
     o_w[e] = take(probe_workspace_bytes(m[b], n[b], k[b]));
     o_est[e] = take(sizeof(double) * m[b]);
+    diag_tiles_all += diag_tiles(m[b], 2 * n[b]);
   }
   const size_t o_hist = take(sizeof(int) * 64 * ne), o_dims = take(sizeof(int64_t) * 3 * ne),
                o_feat = take(sizeof(float) * 64 * ne), o_y = take(sizeof(float) * ne),
@@ -1135,9 +1123,15 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
                o_ft = take(sizeof(FeatTask) * 2 * ne), o_ft_s = take(sizeof(int64_t) * (2 * ne + 1)),
                o_pt = take(sizeof(ProbeTask) * ne), o_ax = take(sizeof(AxpbyTask) * ne),
                o_ax_s = take(sizeof(int64_t) * (ne + 1)), o_mlp = take(mlp_scratch_bytes(ne)),
-               o_emax = take(sizeof(double) * ne);
+               o_emax = take(sizeof(double) * ne), o_s = take(sizeof(int) * ne),
+               o_cap = take(sizeof(int) * ne), o_flag = take(sizeof(int) * ne),
+               o_dt = take(sizeof(DiagTask) * ne), o_dtp = take(sizeof(int) * diag_tiles_all),
+               o_dtl = take(sizeof(int) * diag_tiles_all);
   char *ws = nullptr;
   if ((rc = auto_ws(off, &ws))) return rc;
+  auto h2d = [&](size_t o, const void *src, size_t bytes) {
+    return bytes ? hip_rc(hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st)) : OZAKI_OK;
+  };
 
   // features and selector
   std::vector<ScanTask> scans;
@@ -1161,9 +1155,6 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
   std::vector<int64_t> ss(2 * ne + 1, 0), fs(2 * ne + 1, 0);
   for (size_t t = 0; t < scans.size(); ++t) ss[t + 1] = ss[t] + scan_task_blocks(scans[t]);
   for (size_t t = 0; t < feats.size(); ++t) fs[t + 1] = fs[t] + feat_task_blocks(feats[t]);
-  auto h2d = [&](size_t o, const void *src, size_t bytes) {
-    return bytes ? hip_rc(hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st)) : OZAKI_OK;
-  };
   if ((rc = h2d(o_scan, scans.data(), scans.size() * sizeof(ScanTask)))) return rc;
   if ((rc = h2d(o_scan_s, ss.data(), ss.size() * sizeof(int64_t)))) return rc;
   if ((rc = h2d(o_ft, feats.data(), feats.size() * sizeof(FeatTask)))) return rc;
@@ -1196,19 +1187,21 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     s_of[e] = (int)std::min<double>(OZAKI_S_MAX, std::max<double>(1.0, std::isfinite(v) ? v : OZAKI_S_MAX));
   }
 
-  // emulate, probe, raise
+  int *s_dev = reinterpret_cast<int *>(ws + o_s);
+  int *cap_dev = reinterpret_cast<int *>(ws + o_cap);
+  int *flag_dev = reinterpret_cast<int *>(ws + o_flag);
+  double *emax = reinterpret_cast<double *>(ws + o_emax);
+  const ProbeTask *pt_dev = reinterpret_cast<const ProbeTask *>(ws + o_pt);
   std::vector<int64_t> pending(ne);
   for (int64_t e = 0; e < ne; ++e) pending[e] = e;
-  for (int round = 0; !pending.empty() && round <= OZAKI_S_MAX; ++round) {
+  for (int pass = 0; !pending.empty() && pass <= OZAKI_S_MAX; ++pass) {
     const size_t np = pending.size();
     std::vector<char> ta(np), tb(np);
     std::vector<int64_t> mm(np), nn(np), kk(np), la(np), lb(np), lc(np);
     std::vector<ozaki_z> one(np, ozaki_z{1.0, 0.0}), zero(np, ozaki_z{0.0, 0.0});
     std::vector<const ozaki_z *> pa(np), pb(np);
     std::vector<ozaki_z *> pc(np);
-    std::vector<int> sl(np);
-    std::vector<ProbeTask> pts(np);
-    int64_t nblk[4] = {0, 0, 0, 0};
+    std::vector<int> sl(np), cap(np);
     for (size_t x = 0; x < np; ++x) {
       const int64_t e = pending[x], b = E[e];
       ta[x] = transa[b];
@@ -1223,61 +1216,109 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
       pb[x] = B[b];
       pc[x] = reinterpret_cast<ozaki_z *>(ws + o_P[e]);
       sl[x] = s_of[e];
-      ProbeTask &pt = pts[x];
-      pt = probe_task(view_opA(A[b], transa[b], m[b], k[b], lda[b], true),
-                      view_opB(B[b], transb[b], k[b], n[b], ldb[b], true), true, pc[x], m[b], 2,
-                      0x5eed0000ull + (uint64_t)round, ws + o_w[e],
-                      reinterpret_cast<double *>(ws + o_est[e]));
-      for (int stage = 0; stage < 4; ++stage) {
-        pt.blk[stage] = nblk[stage];
-        nblk[stage] += probe_stage_blocks(pt, stage);
-      }
+      cap[x] = std::min(OZAKI_S_MAX, s_of[e] + 1);
     }
-    // this round's products with alpha = 1, beta = 0 into P: a one-off plan in
-    // the automatic mode's own memory, launched directly (no cache, no graph)
+    // this pass's products at their slice counts, split one slice deeper,
+    // stored unscaled: a one-off plan in the automatic mode's own memory,
+    // launched directly (no cache, no graph)
     BatchedPlan rp;
     rp.dev = dev;
     rp.owns_mem = false;
     std::vector<uint8_t> host;
     if ((rc = build_plan(ta.data(), tb.data(), mm.data(), nn.data(), kk.data(), one.data(), pa.data(),
                          la.data(), pb.data(), lb.data(), zero.data(), pc.data(), lc.data(),
-                         (int64_t)np, sl.data(), g.dev[dev].num_cu, &rp, sel_plan_memory, host)))
+                         (int64_t)np, sl.data(), g.dev[dev].num_cu, &rp, sel_plan_memory, host,
+                         cap.data(), true)))
       return rc;
     if ((rc = hip_rc(hipMemcpyAsync(rp.mem, host.data(), host.size(), hipMemcpyHostToDevice, st))))
       return rc;
     if ((rc = enqueue_plan(rp, st, false))) return rc;
-    if ((rc = h2d(o_pt, pts.data(), np * sizeof(ProbeTask)))) return rc;
-    if ((rc = hip_rc(launch_probe_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt), (int)np,
-                                          nblk, st))))
+
+    // probe tasks (recombined sums scaled on the fly by the feature scan's
+    // codes, which equal the plan's), decision state, one-diagonal tasks
+    const GemmProblem *gps = reinterpret_cast<const GemmProblem *>(host.data() + rp.off_probs);
+    std::vector<ProbeTask> pts(np);
+    std::vector<DiagTask> dts(np);
+    std::vector<int> dtp, dtl;
+    int64_t nblk[4] = {0, 0, 0, 0};
+    for (size_t x = 0; x < np; ++x) {
+      const int64_t e = pending[x], b = E[e];
+      ProbeTask &pt = pts[x];
+      pt = probe_task(view_opA(A[b], transa[b], m[b], k[b], lda[b], true),
+                      view_opB(B[b], transb[b], k[b], n[b], ldb[b], true), true, pc[x], m[b],
+                      kProbeVectors, kProbeSeed, ws + o_w[e],
+                      reinterpret_cast<double *>(ws + o_est[e]));
+      pt.codeA = reinterpret_cast<const int *>(ws + o_codeA[e]);
+      pt.codeB = reinterpret_cast<const int *>(ws + o_codeB[e]);
+      pt.flag = flag_dev;
+      pt.id = (int64_t)x;
+      for (int stage = 0; stage < 4; ++stage) {
+        pt.blk[stage] = nblk[stage];
+        nblk[stage] += probe_stage_blocks(pt, stage);
+      }
+      const GemmProblem &gp = gps[x];
+      dts[x] = DiagTask{gp.SP, gp.SQ, gp.nrbP, gp.nrbQ, gp.nkb, gp.m, gp.nprime, pc[x], 1,
+                        kDigitBits, 0, (int64_t)x};
+      const int64_t nt = diag_tiles(gp.m, gp.nprime);
+      for (int64_t t = 0; t < nt; ++t) {
+        dtp.push_back((int)x);
+        dtl.push_back((int)t);
+      }
+    }
+    std::vector<int> ones(np, 1);
+    if ((rc = h2d(o_s, sl.data(), np * sizeof(int)))) return rc;
+    if ((rc = h2d(o_cap, cap.data(), np * sizeof(int)))) return rc;
+    if ((rc = h2d(o_flag, ones.data(), np * sizeof(int)))) return rc;  // round 0 probes all
+    if ((rc = h2d(o_dt, dts.data(), np * sizeof(DiagTask)))) return rc;
+    if ((rc = h2d(o_dtp, dtp.data(), dtp.size() * sizeof(int)))) return rc;
+    if ((rc = h2d(o_dtl, dtl.data(), dtl.size() * sizeof(int)))) return rc;
+    // one host copy of the task table per round: an asynchronous copy may
+    // read its host buffer after the call returns
+    std::vector<ProbeTask> pts1 = pts;
+    for (int round = 0; round < 2; ++round) {
+      std::vector<ProbeTask> &pr = round == 0 ? pts : pts1;
+      for (size_t x = 0; x < np; ++x) pr[x].seed = kProbeSeed + (uint64_t)(2 * pass + round);
+      if ((rc = h2d(o_pt, pr.data(), np * sizeof(ProbeTask)))) return rc;
+      if ((rc = hip_rc(launch_probe_batched(pt_dev, (int)np, nblk, st)))) return rc;
+      if ((rc = hip_rc(launch_probe_max_batched(pt_dev, (int)np, emax, st)))) return rc;
+      if ((rc = hip_rc(launch_probe_decide(emax, (int64_t)np, g_sel.kappa, g_sel.target, OZAKI_S_MAX,
+                                           s_dev, cap_dev, flag_dev, round == 0 ? 1 : 0, st))))
+        return rc;
+      if (round == 0 &&
+          (rc = hip_rc(launch_add_diagonal(reinterpret_cast<const DiagTask *>(ws + o_dt),
+                                           reinterpret_cast<const int *>(ws + o_dtp),
+                                           reinterpret_cast<const int *>(ws + o_dtl),
+                                           (int64_t)dtp.size(), s_dev, flag_dev, st))))
+        return rc;
+    }
+    std::vector<int> s_fin(np), f_fin(np);
+    if ((rc = hip_rc(hipMemcpyAsync(s_fin.data(), s_dev, np * sizeof(int), hipMemcpyDeviceToHost, st))))
       return rc;
-    if ((rc = hip_rc(launch_probe_max_batched(reinterpret_cast<const ProbeTask *>(ws + o_pt), (int)np,
-                                              reinterpret_cast<double *>(ws + o_emax), st))))
-      return rc;
-    std::vector<double> emax(np);
-    if ((rc = hip_rc(hipMemcpyAsync(emax.data(), ws + o_emax, sizeof(double) * np,
-                                    hipMemcpyDeviceToHost, st))))
+    if ((rc = hip_rc(hipMemcpyAsync(f_fin.data(), flag_dev, np * sizeof(int), hipMemcpyDeviceToHost,
+                                    st))))
       return rc;
     // also keeps `host` and the task vectors alive until their copies are done
     if ((rc = hip_rc(hipStreamSynchronize(st)))) return rc;
     std::vector<int64_t> next;
     for (size_t x = 0; x < np; ++x) {
-      const double mx = emax[x];  // NaN: non-finite inputs, NaN rows, nothing to raise
       const int64_t e = pending[x];
-      if (!std::isnan(mx) && mx * g_sel.kappa > g_sel.target && s_of[e] < OZAKI_S_MAX) {
-        ++s_of[e];
+      s_of[e] = s_fin[x];
+      if (f_fin[x] == 2) {  // missed at the deepest slice of this pass: form it again higher
+        s_of[e] = std::min(OZAKI_S_MAX, s_fin[x] + 1);
         next.push_back(e);
       }
     }
     pending.swap(next);
   }
 
-  // finish: C = alpha P + beta C
+  // finish: C = alpha 2^(e_i + f_j) P + beta C
   std::vector<AxpbyTask> ax(ne);
   std::vector<int64_t> as(ne + 1, 0);
   for (int64_t e = 0; e < ne; ++e) {
     const int64_t b = E[e];
     ax[e] = {ws + o_P[e], C[b], m[b], n[b], ldc[b], alpha[b].re, alpha[b].im, beta[b].re, beta[b].im,
-             (beta[b].re == 0.0 && beta[b].im == 0.0) ? 1 : 0};
+             (beta[b].re == 0.0 && beta[b].im == 0.0) ? 1 : 0,
+             reinterpret_cast<const int *>(ws + o_codeA[e]), reinterpret_cast<const int *>(ws + o_codeB[e])};
     as[e + 1] = as[e] + axpby_task_blocks(ax[e]);
     used[b] = s_of[e];
   }
@@ -1918,9 +1959,6 @@ int ozaki_finalize(void) {
       (void)hipSetDevice(cur);
       g_lu_flag[d] = nullptr;
     }
-    if (g_blas[d] == nullptr) continue;
-    if (rocblas_destroy_handle(g_blas[d]) != rocblas_status_success) rc = OZAKI_ERR_INTERNAL;
-    g_blas[d] = nullptr;
   }
   return rc;
 }

@@ -252,9 +252,12 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //   5: as 4 with the reads of 3 (4 and 5 fall back to 2 for S >= 11)
 //   6: as 2 with two 32-row blocks of A' per wave (tile 128 j' x 128 i): each
 //      B' fragment feeds two MFMAs; S <= 6 only (else configuration 2)
-// A tuning id is 2 * configuration + tile order (0: consecutive tiles walk
-// down the rows i, 1: along the columns j').
+// A tuning id below 14 is 2 * configuration + tile order (0: consecutive
+// tiles walk down the rows i, 1: along the columns j'); ids 14 .. 20 are
+// configurations 0 .. 6 with the grouped tile order 2 (see tile_coords).
 constexpr int kNumCfg = 7;
+constexpr int id_cfg(int id) { return id < 2 * kNumCfg ? id >> 1 : id - 2 * kNumCfg; }
+constexpr int id_order(int id) { return id < 2 * kNumCfg ? (id & 1) : 2; }
 
 template <int CFG>
 struct Pick;
@@ -321,7 +324,7 @@ constexpr int waves_of() {
 
 int64_t kb_chunk_for(int S, bool b8) { return chunk_blocks(S, b8 ? 128 : 127); }
 
-int gemm_num_configs() { return 2 * kNumCfg; }
+int gemm_num_configs() { return 3 * kNumCfg; }
 
 size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
   // the largest per-workgroup carry space over the configurations, so that a
@@ -334,7 +337,7 @@ size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
 
 int64_t gemm_tiles(int S, int cfg, int64_t m, int64_t nprime) {
   int64_t BJ, BI;
-  switch (cfg / 2) {
+  switch (id_cfg(cfg)) {
     case 1: BJ = 32 * Pick<1>::WJ; BI = 32 * Pick<1>::WI * Pick<1>::IB; break;
     case 2: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
     case 3: BJ = 32 * Pick<2>::WJ; BI = 32 * Pick<2>::WI * Pick<2>::IB; break;
@@ -368,8 +371,8 @@ hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, 
 
 hipError_t launch_ozgemm(int S, int tune_id, const GemmArgs &a0, int num_cu, hipStream_t st) {
   GemmArgs a = a0;
-  a.order = tune_id & 1;
-  const int cfg = tune_id >> 1;
+  a.order = id_order(tune_id);
+  const int cfg = id_cfg(tune_id);
   switch (S) {
 #define OZ_CASE(N) \
   case N: return launch_s<N>(cfg, a, num_cu, st);

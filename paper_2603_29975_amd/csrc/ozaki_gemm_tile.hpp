@@ -52,13 +52,19 @@ __host__ __device__ constexpr int64_t chunk_blocks(int S, int dmax = 127) {
 // space `ws` (S * 16 * 64 int64, lane-interleaved); the accumulators restart
 // at zero. Device-scope atomics keep the traffic in L2, away from stale lines
 // of the non-coherent vector L1.
+// The lane's base address goes through an empty asm statement: the S x 16
+// addresses are then formed here, one at a time, instead of being hoisted out
+// of the contraction loop, where keeping them live costs 2 S x 16 registers
+// and the compiler spills.
 template <int S>
 __device__ __forceinline__ void carry_block(v16i (&acc)[S], int64_t *ws, int lane, bool first) {
+  int64_t *q = ws + lane;
+  asm volatile("" : "+v"(q));
 #pragma unroll
   for (int t = 0; t < S; ++t) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      int64_t *p = ws + (t * 16 + r) * 64 + lane;
+      int64_t *p = q + (t * 16 + r) * 64;
       if (first)
         __hip_atomic_store(p, (int64_t)acc[t][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else
@@ -82,10 +88,11 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
   const bool row_ok = i < a.m;
   const int codeA = row_ok ? a.codeA[i] : 0;
 
+  const int64_t *q = ws + lane;
+  if constexpr (CHUNKED) asm volatile("" : "+v"(q));  // as in carry_block
   auto total = [&](int t, int r) -> int64_t {
     if constexpr (CHUNKED)
-      return __hip_atomic_load(ws + (t * 16 + r) * 64 + lane, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      return __hip_atomic_load(q + (t * 16 + r) * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return (int64_t)acc[t][r];
   };
 
@@ -118,10 +125,38 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
     for (int t = 0; t < S; ++t)
       acc64 = add_rn(acc64, ldexp((double)total(t, r), a.woff - a.wbits * (t + 2)));
     val[r] = acc64;
+    // chunked: the S int64 totals of one entry at a time (issuing all 16 S
+    // loads at once needs 32 S registers)
+    if constexpr (CHUNKED) __builtin_amdgcn_sched_barrier(0);
   }
   if (!row_ok) return;
   const int ea = code_exp(codeA);
   const bool bad_i = code_bad(codeA);
+
+  if (a.unscaled) {
+    // the recombined sums as they are (NaN for non-finite rows/columns): a
+    // later diagonal adds to them exactly as the loop above would have
+    if (a.cplx) {
+      double2 *C = reinterpret_cast<double2 *>(a.C);
+      const int64_t n = a.nprime >> 1;
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int64_t j = (jbase + 8 * (r >> 2) + (r & 3)) >> 1;
+        if (j >= n) continue;
+        const bool bad = bad_i || code_bad(a.codeB[j]);
+        C[i + j * a.ldc] = bad ? make_double2(qnan(), qnan()) : make_double2(val[r], val[r + 1]);
+      }
+    } else {
+      double *C = reinterpret_cast<double *>(a.C);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t j = jbase + 8 * (r >> 2) + (r & 3);
+        if (j >= a.nprime) continue;
+        C[i + j * a.ldc] = (bad_i || code_bad(a.codeB[j])) ? qnan() : val[r];
+      }
+    }
+    return;
+  }
 
   if (a.cplx) {
     double2 *C = reinterpret_cast<double2 *>(a.C);
@@ -170,17 +205,28 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
 }
 
 // Output tile (tj, ti) of tile number `local` in a grid of tiles BJ x BI:
-// order 0 walks down the rows i first, order 1 along the columns j' first.
+// order 0 walks down the rows i first, order 1 along the columns j' first,
+// order 2 in groups of 16 tile rows, down the rows of a group first (the
+// tiles in flight at once then share 16 A' stripes and few B' stripes, which
+// keeps long contractions in the caches instead of streaming every B' stripe
+// once per round).
 __device__ __forceinline__ void tile_coords(int64_t local, int order, int64_t m, int64_t nprime,
                                             int BJ, int BI, int64_t &tj, int64_t &ti) {
+  const int64_t nti = (m + BI - 1) / BI;
   if (order == 0) {
-    const int64_t nti = (m + BI - 1) / BI;
     tj = local / nti;
     ti = local % nti;
-  } else {
+  } else if (order == 1) {
     const int64_t ntj = (nprime + BJ - 1) / BJ;
     ti = local / ntj;
     tj = local % ntj;
+  } else {
+    constexpr int64_t kGroup = 16;
+    const int64_t ntj = (nprime + BJ - 1) / BJ;
+    const int64_t g = local / (kGroup * ntj), r = local - g * (kGroup * ntj);
+    const int64_t gh = nti - g * kGroup < kGroup ? nti - g * kGroup : kGroup;
+    ti = g * kGroup + r % gh;
+    tj = r / gh;
   }
 }
 

@@ -72,6 +72,7 @@ struct GemmProblem {
   void *C;
   int64_t ldc;
   int64_t *raw;  // raw diagonal output (debug) or nullptr
+  int unscaled;  // store the recombined sum itself (no 2^(e_i + f_j), no alpha/beta)
 };
 
 // Kernel arguments: either one problem (grouped == 0) or a table of problems
@@ -147,6 +148,12 @@ struct ProbeTask {
   double *w, *ub, *est, *p1, *p2;
   int64_t chl, chj, ncl, ncj;
   int64_t blk[4];  // batched: first block of this task in each stage
+  // optional: C holds recombined sums still to be scaled by 2^(e_i + f_j)
+  // (exponent codes of its rows and columns), and a skip flag (the task runs
+  // only while flag[id] == 1)
+  const int *codeA, *codeB;
+  const int *flag;
+  int64_t id;
 };
 // C = alpha P + beta C over complex problems (P: m x n, leading dimension m).
 struct AxpbyTask {
@@ -155,6 +162,7 @@ struct AxpbyTask {
   int64_t m, n, ldc;
   double ar, ai, br, bi;
   int beta_zero;
+  const int *codeA, *codeB;  // optional: P = RN-scaled P 2^(e_i + f_j) first
 };
 int64_t axpby_task_blocks(const AxpbyTask &t);
 // Scratch bytes of one probe, its task (scratch at ws), blocks per stage, and
@@ -171,6 +179,31 @@ hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, in
 int probe_max_vectors();
 hipError_t launch_probe_max_batched(const ProbeTask *tasks, int ntasks, double *out,
                                     hipStream_t st);
+// Automatic-mode decision for n problems after a probe round: flag[e] (the
+// problems probed this round: all when `first`, else those with flag[e] == 1)
+// becomes 1 when emax[e] * kappa > target and s[e] < cap[e] (then s[e] is
+// raised by one), 2 when the target is missed but s[e] == cap[e] < smax,
+// else 0.
+hipError_t launch_probe_decide(const double *emax, int64_t n, double kappa, double target,
+                               int smax, int *s, const int *cap, int *flag, int first,
+                               hipStream_t st);
+// One more diagonal for the problems with flag[id] == 1: diagonal d = s[id] + 1
+// (trunc-7 slices, the new slice count s[id]) over the problem's packed
+// operands, added to its recombined sums P (unscaled, column-major, leading
+// dimension m) as P = RN(P + S_d 2^(woff - wbits d)). Tiles of 64 x 64 (j' x
+// i) from a tile table.
+struct DiagTask {
+  const int8_t *SP, *SQ;  // packed B' and A' (as GemmProblem)
+  int64_t nrbP, nrbQ, nkb;
+  int64_t m, nprime;
+  void *P;
+  int cplx;
+  int wbits, woff;
+  int64_t id;
+};
+int64_t diag_tiles(int64_t m, int64_t nprime);
+hipError_t launch_add_diagonal(const DiagTask *tasks, const int *tile_task, const int *tile_local,
+                               int64_t ntiles, const int *s, const int *flag, hipStream_t st);
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
                         int nv, uint64_t seed, void *ws, double *est, hipStream_t st);
 
@@ -185,23 +218,28 @@ int crt_log2_floor(int n);
 // beta = min(63, floor((floor(log2 M) - 1 - ceil(log2 K')) / 2)); below 1
 // means too few moduli for the contraction length.
 int crt_beta(int n, int64_t kprime);
-// Residues of X' (rows of op(A), or of B' for side_b) into n planes of
-// `plane` bytes, row-major with ldx bytes per row (ldx a multiple of 128, the
-// contraction entries K' <= l < ldx written as zero).
+// Residues of X' (rows of op(A), or of B' for side_b) into n planes in the
+// packed fragment layout of the slices (nrb 32-row blocks, nkb 32-entry
+// contraction blocks, nkb a multiple of 4; plane k at out + k nrb nkb KiB);
+// padded rows and contraction entries hold zero residues.
 hipError_t launch_residues(const View &v, bool cplx, bool side_b, const int *code, int n, int beta,
-                           int8_t *out, int64_t ldx, int64_t plane, hipStream_t st);
-struct CrtArgs {
-  const int32_t *Cint;  // n planes of m x n' INT32 products, column j' at Cint + j' m
-  int64_t plane;        // elements per plane
-  int64_t m, n;         // output rows and columns
+                           int8_t *out, int64_t nrb, int64_t nkb, hipStream_t st);
+// Fused Ozaki-II product: per output tile the n modular INT8 products, each
+// reduced at once to its Garner digit, then the rebuilt integer rounded to
+// FP64, scaled by 2^(e_i + f_j - 2 beta) and alpha/beta applied.
+struct Oz2Args {
+  const int8_t *RA, *RB;  // packed residue planes of A' (nrbQ blocks) and B' (nrbP blocks)
+  int64_t nrbQ, nrbP, nkb;
+  int64_t m, nprime;      // output rows i < m, output "rows" j' < nprime (n or 2n)
   const int *codeA, *codeB;
   int beta;
   double ar, ai, br, bi;
   int beta_zero;
+  int cplx;
   void *C;
   int64_t ldc;
 };
-hipError_t launch_crt(int n, bool cplx, const CrtArgs &a, hipStream_t st);
+hipError_t launch_oz2gemm(int n, const Oz2Args &a, int num_cu, hipStream_t st);
 
 // Blocked LU and inverse (see ozaki_lu.hip): one pivot column (pivot search,
 // swap over the panel columns [p0, p1) and panel update), the panel's

@@ -18,14 +18,15 @@ __global__ void __launch_bounds__(256) k_fill_i32(int *p, int64_t n, int value) 
 // Pseudo-random INT8 digits in [-127, 127] (SplitMix64 finaliser of the byte
 // index): stand-in slice data for timing the slice GEMM, whose power draw and
 // clock depend on the operand bits.
+// Grid-stride: the fills of large workspaces exceed the grid size limit.
 __global__ void __launch_bounds__(256) k_fill_digits(int8_t *p, int64_t n, uint64_t seed) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  uint64_t z = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(i + 1);
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  z ^= z >> 31;
-  p[i] = (int8_t)((int)(z % 255u) - 127);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    p[i] = (int8_t)((int)(z % 255u) - 127);
+  }
 }
 
 template <bool CPLX>
@@ -482,7 +483,8 @@ hipError_t launch_fill_i32(int *p, int64_t n, int value, hipStream_t st) {
 
 hipError_t launch_fill_digits(int8_t *p, int64_t n, uint64_t seed, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_digits, dim3(grid1(n)), dim3(256), 0, st, p, n, seed);
+  hipLaunchKernelGGL(k_fill_digits, dim3((unsigned)std::min<int64_t>(grid1(n), 1 << 20)), dim3(256),
+                     0, st, p, n, seed);
   return hipGetLastError();
 }
 

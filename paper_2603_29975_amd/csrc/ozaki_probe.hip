@@ -194,6 +194,11 @@ __device__ void rows_part(const ProbeTask &tk, int64_t idx) {
       } else {
         cr = reinterpret_cast<const double *>(tk.C)[i + j * tk.ldc];
       }
+      if (tk.codeA != nullptr) {
+        const int sc = code_exp(tk.codeA[i]) + code_exp(tk.codeB[j]);
+        cr = ldexp(cr, sc);
+        ci = ldexp(ci, sc);
+      }
   #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const double s = sign_of(tk.seed, v, N, j);
@@ -279,6 +284,7 @@ __global__ void __launch_bounds__(256) k_probe_stage_batched(const ProbeTask *ta
       hi = mid - 1;
   }
   const ProbeTask &tk = tasks[lo];
+  if (tk.flag != nullptr && tk.flag[tk.id] != 1) return;
   run_stage(tk, stage, (b - tk.blk[stage]) * 256 + threadIdx.x);
 }
 
@@ -298,6 +304,7 @@ __device__ __forceinline__ int find_task3(const int64_t *start, int ntasks, int6
 // one workgroup per task.
 __global__ void __launch_bounds__(256) k_probe_max_batched(const ProbeTask *tasks, double *out) {
   const ProbeTask &tk = tasks[blockIdx.x];
+  if (tk.flag != nullptr && tk.flag[tk.id] != 1) return;
   const int64_t M = tk.va.R;
   double mx = 0.0;
   bool nan = false;
@@ -333,7 +340,11 @@ __global__ void __launch_bounds__(256) k_axpby_batched(const AxpbyTask *tasks, c
   const int64_t idx = (blockIdx.x - start[t]) * 256 + threadIdx.x;
   if (idx >= tk.m * tk.n) return;
   const int64_t i = idx % tk.m, j = idx / tk.m;
-  const double2 p = reinterpret_cast<const double2 *>(tk.P)[i + j * tk.m];
+  double2 p = reinterpret_cast<const double2 *>(tk.P)[i + j * tk.m];
+  if (tk.codeA != nullptr) {
+    const int sc = code_exp(tk.codeA[i]) + code_exp(tk.codeB[j]);
+    p = make_double2(ldexp(p.x, sc), ldexp(p.y, sc));
+  }
   double2 *cp = reinterpret_cast<double2 *>(tk.C) + i + j * tk.ldc;
   double re = sub_rn(mul_rn(tk.ar, p.x), mul_rn(tk.ai, p.y));
   double im = add_rn(mul_rn(tk.ar, p.y), mul_rn(tk.ai, p.x));
@@ -343,6 +354,24 @@ __global__ void __launch_bounds__(256) k_axpby_batched(const AxpbyTask *tasks, c
     im = add_rn(im, add_rn(mul_rn(tk.br, z.y), mul_rn(tk.bi, z.x)));
   }
   *cp = make_double2(re, im);
+}
+
+__global__ void __launch_bounds__(256) k_probe_decide(const double *emax, int64_t n, double kappa,
+                                                      double target, int smax, int *s,
+                                                      const int *cap, int *flag, int first) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  if (!first && flag[e] != 1) return;
+  const double mx = emax[e];  // NaN: non-finite inputs, nothing to raise
+  const bool miss = !isnan(mx) && mx * kappa > target;
+  int f = 0;
+  if (miss && s[e] < cap[e]) {
+    f = 1;
+    s[e] += 1;
+  } else if (miss && s[e] < smax) {
+    f = 2;
+  }
+  flag[e] = f;
 }
 
 }  // namespace
@@ -428,6 +457,15 @@ hipError_t launch_axpby_batched(const AxpbyTask *tasks, const int64_t *start, in
 }
 
 int probe_max_vectors() { return kMaxVec; }
+
+hipError_t launch_probe_decide(const double *emax, int64_t n, double kappa, double target,
+                               int smax, int *s, const int *cap, int *flag, int first,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe_decide, dim3((unsigned)blocks(n)), dim3(256), 0, st, emax, n, kappa,
+                     target, smax, s, cap, flag, first);
+  return hipGetLastError();
+}
 
 hipError_t launch_probe(const View &va, const View &vb, bool cplx, const void *C, int64_t ldc,
                         int nv, uint64_t seed, void *ws, double *est, hipStream_t st) {
