@@ -462,8 +462,8 @@ def run_single(args):
     pairs = s if ozaki2 else s * (s + 1) // 2
     int8_ops = pairs * flops
     if ozaki2:
-        kernel = (f"batched INT8 GEMM over {s} moduli; residue and CRT kernels are timed in "
-                  "phases_ms")
+        kernel = (f"fused INT8 modular products over {s} moduli + CRT rebuild + FP64 epilogue "
+                  "(k_oz2gemm); the residue kernels are timed in phases_ms")
         traffic = None
     else:
         kernel = ("fused INT8 slice-pair GEMM + FP64 recombination (k_ozgemm, tuning id "
@@ -484,6 +484,18 @@ def run_single(args):
                       "calls": reps, "tflops": round(ntf, 2),
                       "frac_of_fp64_peak": round(ntf / FP64_PEAK_TFLOPS, 4)}
         log(f"native: {nms:.3f} ms/call  {ntf:.2f} TFLOP/s")
+        # context: the vendor library's FP64 GEMM on the same buffers (torch.matmul,
+        # i.e. rocBLAS); C^T = op(B)^T op(A)^T in the row-major view of the buffers
+        Cl = torch.empty_like(Cn)
+        lib = lambda: torch.matmul(Bd, Ad, out=Cl)
+        lib()
+        torch.cuda.synchronize()
+        lms = wall(lib, reps)
+        del Cl
+        native_rec["vendor_library_fp64"] = {
+            "kernel": "torch.matmul (rocBLAS) on the same buffers, for context",
+            "ms_per_call": round(lms, 4), "tflops": round(flops / (lms * 1e-3) / 1e12, 2)}
+        log(f"vendor library FP64: {lms:.3f} ms/call  {flops / (lms * 1e-3) / 1e12:.2f} TFLOP/s")
 
     # ------------------------------------------------ host-BLAS interposer
     interposer = None

@@ -19,7 +19,11 @@
 // Tiles: 256 threads = 2 x 2 waves, wave tile 64 (j') x 64 (i) = 4 x 4 MFMA
 // blocks of 16 x 16, contraction 16 per stage, LDS double buffered with a
 // register prefetch of the next stage. Operands are gathered from their BLAS
-// layout into LDS with the unit-stride dimension on consecutive lanes.
+// layout into LDS with the unit-stride dimension on consecutive lanes. The
+// launch bounds ask for two workgroups per CU (<= 256 registers per wave):
+// left free, the compiler takes 334 (accumulators in AGPRs), which allows one
+// wave per SIMD and exposes every LDS and barrier wait (16384^3 complex: 26.6
+// TFLOP/s at one wave per SIMD, 43.1 at two).
 #include "ozaki_internal.hpp"
 
 namespace oz {
@@ -58,7 +62,7 @@ __device__ __forceinline__ typename Loader<CPLX>::T load_elem(const View &v, int
 }
 
 template <bool CPLX>
-__global__ void __launch_bounds__(NTH) k_native(NativeArgs a) {
+__global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
   using LD = Loader<CPLX>;
   using T = typename LD::T;
   __shared__ double ldsP[2][NBK * LDJ];

@@ -29,12 +29,17 @@ S_HI = 12
 KAPPA = 8.0      # probe safety factor used when the weights file stores none
 
 
-def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32):
-    """m, n from mn_choices; k = 32 j with P(j) ~ 1/j (the batched law)."""
+def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32, mn_law=False):
+    """k = 32 j with P(j) ~ 1/j (the batched law); m, n from mn_choices, or
+    with mn_law from the same law as k (32..1024, the sizes of the batch)."""
     j = np.arange(1, kmax_j + 1)
     p = (1.0 / j) / np.sum(1.0 / j)
-    m = rng.choice(mn_choices, count)
-    n = rng.choice(mn_choices, count)
+    if mn_law:
+        m = rng.choice(j, count, p=p) * 32
+        n = rng.choice(j, count, p=p) * 32
+    else:
+        m = rng.choice(mn_choices, count)
+        n = rng.choice(mn_choices, count)
     k = rng.choice(j, count, p=p) * 32
     return m.astype(np.int64), n.astype(np.int64), k.astype(np.int64)
 
@@ -61,13 +66,13 @@ def kkr_rows(m, n, k, seed, block=32):
     return A[:m], B
 
 
-def generate_pairs(count: int, seed: int, mn_choices=(32, 64)):
+def generate_pairs(count: int, seed: int, mn_choices=(32, 64), mn_law=False):
     """Complex (A, B) pairs from four families: per-entry binade spread,
     per-matrix exponent spread with row/column scaling, Gaussian with
     power-of-two row/column scaling, and KKR-shaped blocks."""
     from workloads import batched_problems, complex_normal
     rng = np.random.default_rng(seed)
-    ms, ns, ks = pair_sizes(rng, count, mn_choices)
+    ms, ns, ks = pair_sizes(rng, count, mn_choices, mn_law=mn_law)
     fam = rng.integers(0, 4, count)
     pairs = []
     for i in range(count):
@@ -92,7 +97,7 @@ def generate_pairs(count: int, seed: int, mn_choices=(32, 64)):
     return pairs
 
 
-def generate_pairs_device(count: int, seed: int, mn_choices=(32, 64)):
+def generate_pairs_device(count: int, seed: int, mn_choices=(32, 64), mn_law=False):
     """The same four families as generate_pairs, drawn on the GPU with a seeded
     torch generator (training data only; the oracle-checked workloads use the
     numpy generators). Returns a list of (A, B) complex128 CUDA tensors."""
@@ -100,7 +105,7 @@ def generate_pairs_device(count: int, seed: int, mn_choices=(32, 64)):
     rng = np.random.default_rng(seed)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(int(seed))
-    ms, ns, ks = pair_sizes(rng, count, mn_choices)
+    ms, ns, ks = pair_sizes(rng, count, mn_choices, mn_law=mn_law)
     fam = rng.integers(0, 4, count)
     two = torch.tensor(2.0, dtype=torch.float64, device="cuda")
 
@@ -307,6 +312,95 @@ def calibrate_margin(pred, labels, coverage=0.99):
     return 6.0
 
 
+PROBE_SEED = 0x5EED0000   # the automatic mode probes round r with seed PROBE_SEED + r
+PROBE_VECTORS = 2
+
+
+def probe_table(pairs, slices, seeds):
+    """For each pair, the emulated product at slices[i] (the batched entry
+    point, alpha = 1, beta = 0) and, for every r in `seeds`, the residual
+    probe's largest row estimate with the automatic mode's probe
+    (PROBE_VECTORS sign vectors, seed PROBE_SEED + r). Returns an array
+    (len(pairs), len(seeds))."""
+    import torch
+    from . import ozaki_probe
+    db = DeviceBatch(pairs)
+    nb = len(pairs)
+    pa, pb = db.ptrs(db.A, db.oa, 16), db.ptrs(db.B, db.ob, 16)
+    out = torch.zeros(db.nc, dtype=torch.complex128, device="cuda")
+    po = db.ptrs(out, db.oc, 16)
+    rc = ozaki_zgemm_batched(["N"] * nb, ["N"] * nb, db.m, db.n, db.k, [1.0] * nb, pa, db.m, pb,
+                             db.k, [0.0] * nb, po, db.m, nb, [int(x) for x in slices])
+    if rc:
+        raise OzakiError(rc, "ozaki_zgemm_batched")
+    est = torch.zeros((len(seeds), int(db.m.max())), dtype=torch.float64, device="cuda")
+    res = torch.zeros((nb, len(seeds)), dtype=torch.float64, device="cuda")
+    for b in range(nb):
+        m, n, k = int(db.m[b]), int(db.n[b]), int(db.k[b])
+        for x, r in enumerate(seeds):
+            rc = ozaki_probe("z", "N", "N", m, n, k, pa[b], m, pb[b], k, po[b], m, PROBE_VECTORS,
+                             PROBE_SEED + r, est[x])
+            if rc:
+                raise OzakiError(rc, "ozaki_probe")
+        res[b] = est[:, :m].max(dim=1).values
+    return res.cpu().numpy()
+
+
+def simulate_auto(pred, margin, kappa, errs, est, target, s_lo=S_LO):
+    """The automatic mode on labelled pairs, from tables: errs[i, s - s_lo]
+    (componentwise error at s slices) and est[i, s - s_lo, r] (the probe's
+    largest row estimate at s with seed PROBE_SEED + r). Pass p starts at
+    s_p (s_0 = ceil(pred + margin)), probes with seed 2p, raises to s_p + 1
+    if est * kappa > target, probes that with seed 2p + 1, and if the target is
+    still missed starts pass p + 1 at s_p + 2 (up to S_HI). Returns the final
+    slice counts and whether each pair then meets the target."""
+    n = len(pred)
+    s = np.clip(np.ceil(pred + margin), 1, S_HI).astype(int)
+    s = np.maximum(s, s_lo)
+    final = s.copy()
+    active = np.ones(n, dtype=bool)
+    idx = np.arange(n)
+    for p in range(4):
+        if not active.any():
+            break
+        r0 = min(2 * p, est.shape[2] - 1)
+        r1 = min(2 * p + 1, est.shape[2] - 1)
+        e0 = est[idx, final - s_lo, r0]
+        raise0 = active & (e0 * kappa > target) & (final < S_HI)
+        final = np.where(raise0, final + 1, final)
+        e1 = est[idx, final - s_lo, r1]
+        again = raise0 & (e1 * kappa > target) & (final < S_HI)
+        final = np.where(again, np.minimum(final + 1, S_HI), final)
+        active = again
+    ok = errs[idx, final - s_lo] <= target
+    return final, ok
+
+
+def calibrate_auto(pred, errs, est, work, target, log=None):
+    """Margin and probe safety factor kappa for the automatic mode, from
+    held-out labelled pairs: among margins in [-1, 3] (steps of 0.05) and
+    kappa in {1, 2, 4, ..., 2^14}, the setting with the least INT8 work
+    (sum of s(s+1)/2 x work[i]) under which every pair meets the target
+    after the mode's raises (simulate_auto). Returns (margin, kappa, stats)."""
+    best = None
+    tri = lambda v: v * (v + 1) / 2.0
+    for margin in np.arange(-1.0, 3.0001, 0.05):
+        for kappa in 2.0 ** np.arange(0, 15):
+            final, ok = simulate_auto(pred, margin, kappa, errs, est, target)
+            if not ok.all():
+                continue
+            w = float(np.sum(tri(final) * work))
+            if best is None or w < best[0]:
+                best = (w, float(margin), float(kappa), float(final.mean()))
+            break   # a larger kappa only raises more
+    if best is None:
+        raise RuntimeError("no margin and kappa meet the target on every held-out pair")
+    w, margin, kappa, mean_s = best
+    if log:
+        log(f"auto calibration: margin {margin:.2f}, kappa {kappa:g}, mean final s {mean_s:.3f}")
+    return margin, kappa, {"mean_final_s": mean_s, "int8_work": w}
+
+
 def save(path, theta, margin, target, meta):
     np.savez(path, theta=np.asarray(theta, dtype=np.float32), margin=np.float32(margin),
              target=np.float64(target), **{k: np.asarray(v) for k, v in meta.items()})
@@ -399,10 +493,51 @@ def evaluate_gain(theta, margin, target, kappa=8.0, pairs=None, steps=5, log=Non
     return res
 
 
+LAW_S_LO, LAW_S_HI = 5, 11   # label range of the pairs with batch-sized m, n
+
+
+def labelled_set(count, seed, target, law_frac, chunk=4096, log=None, keep_pairs=False):
+    """`count` generated pairs (a fraction law_frac of each chunk with m, n
+    from the batch's size law, the rest with m, n in {32, 64}), labelled and
+    featurised on the GPU. Returns (features, labels) and, with keep_pairs,
+    the error table over S_LO..S_HI and the pairs."""
+    import torch
+    feats_l, labels_l, errs_l, kept = [], [], [], []
+    for c0 in range(0, count, chunk):
+        cnt = min(chunk, count - c0)
+        nlaw = int(round(cnt * law_frac))
+        for part, (num, law) in enumerate(((cnt - nlaw, False), (nlaw, True))):
+            if num == 0:
+                continue
+            pairs = generate_pairs_device(num, seed * 1000003 + 2 * c0 + part, mn_law=law)
+            lo, hi = (LAW_S_LO, LAW_S_HI) if law else (S_LO, S_HI)
+            lab, err, f = label_pairs(pairs, target, s_lo=lo, s_hi=hi, with_features=True)
+            feats_l.append(f)
+            labels_l.append(lab)
+            # errors over S_LO..S_HI: below lo counted as misses, above hi as at hi
+            full = np.full((len(pairs), S_HI - S_LO + 1), np.inf)
+            full[:, lo - S_LO:hi - S_LO + 1] = err
+            full[:, hi - S_LO + 1:] = err[:, -1:]
+            errs_l.append(full)
+            if keep_pairs:
+                kept += pairs
+            del pairs
+        if log and (c0 // chunk) % 8 == 0:
+            log(f"{c0 + cnt} pairs labelled")
+    out = (torch.cat(feats_l), np.concatenate(labels_l))
+    if keep_pairs:
+        out = out + (np.concatenate(errs_l), kept)
+    return out
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="train the slice-count selector on the GPU")
     ap.add_argument("--pairs", type=int, default=200_000)
+    ap.add_argument("--law-frac", type=float, default=0.1,
+                    help="share of pairs whose m, n follow the batch's size law (32..1024)")
+    ap.add_argument("--kappa-pairs", type=int, default=16384,
+                    help="held-out pairs (seed + 1) that calibrate the probe's safety factor")
     ap.add_argument("--target", type=float, default=1e-11)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--out", required=True)
@@ -413,35 +548,44 @@ def main(argv=None):
     def log(*a):
         print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
 
-    ntrain = int(args.pairs * 0.9)
     from . import ozaki_batched_graphs
-    import torch
     ozaki_batched_graphs(False)          # one-off batches: no graph capture
-    chunk = 4096
-    feats_l, labels_l = [], []
-    for c0 in range(0, args.pairs, chunk):
-        cnt = min(chunk, args.pairs - c0)
-        pairs = generate_pairs_device(cnt, args.seed * 1000003 + c0)
-        lab, _, f = label_pairs(pairs, args.target, with_features=True)
-        feats_l.append(f)
-        labels_l.append(lab)
-        del pairs
-        if (c0 // chunk) % 8 == 0:
-            log(f"{c0 + cnt} pairs labelled")
-    feats = torch.cat(feats_l)
-    labels = np.concatenate(labels_l)
-    ozaki_batched_graphs(True)
+    feats, labels = labelled_set(args.pairs, args.seed, args.target, args.law_frac, log=log)
+    # chunks mix both size families, so a random split keeps both in validation
+    perm = np.random.default_rng(args.seed).permutation(len(labels))
+    ntrain = int(len(labels) * 0.9)
+    tr, va = perm[:ntrain], perm[ntrain:]
+    import torch
+    tr_d, va_d = torch.from_numpy(tr).cuda(), torch.from_numpy(va).cuda()
     log(f"label histogram (s = {S_LO}..{S_HI + 1}) {np.bincount(labels, minlength=S_HI + 2)[S_LO:]}")
     log("training")
-    theta = train(feats[:ntrain], labels[:ntrain], epochs=args.epochs, seed=args.seed, log=log)
-    pred = predict(theta, feats[ntrain:])
-    margin = calibrate_margin(pred, labels[ntrain:])
+    theta = train(feats[tr_d], labels[tr], epochs=args.epochs, seed=args.seed, log=log)
+    pred = predict(theta, feats[va_d])
+    margin = calibrate_margin(pred, labels[va])
     s_val = np.clip(np.ceil(pred + margin), 1, S_HI)
-    log(f"validation: margin {margin:.2f}, coverage {np.mean(s_val >= np.minimum(labels[ntrain:], S_HI)):.4f}, "
-        f"mean predicted s {s_val.mean():.3f}, mean label {labels[ntrain:].mean():.3f}")
-    save(args.out, theta, margin, args.target,
-         {"pairs": args.pairs, "seed": args.seed, "val_coverage": np.mean(s_val >= np.minimum(labels[ntrain:], S_HI)),
-          "val_mean_s": s_val.mean(), "val_mean_label": labels[ntrain:].mean()})
+    cov = float(np.mean(s_val >= np.minimum(labels[va], S_HI)))
+    log(f"validation: margin {margin:.2f}, coverage {cov:.4f}, "
+        f"mean predicted s {s_val.mean():.3f}, mean label {labels[va].mean():.3f}")
+    # the automatic mode's margin and probe safety factor from pairs of another
+    # seed: the mode simulated from their error tables and probe estimates
+    kfeat, klab, kerrs, kpairs = labelled_set(args.kappa_pairs, args.seed + 1, args.target,
+                                              args.law_frac, keep_pairs=True)
+    kpred = predict(theta, kfeat)
+    nk = len(kpairs)
+    est = np.full((nk, S_HI - S_LO + 1, 4), np.inf)
+    for sv in range(S_LO, S_HI + 1):
+        est[:, sv - S_LO, :] = probe_table(kpairs, [sv] * nk, seeds=(0, 1, 2, 3))
+    work = np.array([8.0 * A.shape[0] * B.shape[1] * A.shape[1] for A, B in kpairs])
+    auto_margin, kappa, st = calibrate_auto(kpred, kerrs, est, work, args.target, log=log)
+    s_pred = np.clip(np.ceil(kpred + auto_margin), 1, S_HI)
+    log(f"held-out pairs {nk}: mean label {np.mean(np.minimum(klab, S_HI)):.3f}, mean predicted s "
+        f"{s_pred.mean():.3f}, mean final s {st['mean_final_s']:.3f}")
+    ozaki_batched_graphs(True)
+    save(args.out, theta, auto_margin, args.target,
+         {"pairs": args.pairs, "seed": args.seed, "law_frac": args.law_frac, "val_coverage": cov,
+          "coverage_margin": margin, "val_mean_s": s_val.mean(),
+          "val_mean_label": labels[va].mean(), "kappa": kappa, "kappa_pairs": nk,
+          "calib_mean_final_s": st["mean_final_s"]})
     log(f"saved {args.out}")
 
 
