@@ -71,7 +71,8 @@ enum ozaki_status {
   OZAKI_ERR_INTERNAL = 5,
   OZAKI_ERR_NO_SELECTOR = 6,  /* automatic slice selection without a loaded selector */
   OZAKI_ERR_IO = 7,           /* tuning cache file missing, unwritable or malformed */
-  OZAKI_ERR_SINGULAR = 8      /* ozaki_zgetrf met an exactly zero pivot */
+  OZAKI_ERR_SINGULAR = 8,     /* ozaki_zgetrf met an exactly zero pivot */
+  OZAKI_ERR_TOO_LARGE = 9     /* ozaki_zgemm_noalloc: scratch beyond its fixed array */
 };
 
 /*
@@ -89,6 +90,28 @@ int ozaki_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
 int ozaki_zgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                 ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B, int64_t ldb,
                 ozaki_z beta, ozaki_z *C, int64_t ldc, int slices);
+
+/*
+ * ozaki_zgemm without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, numbering, slice kind, tile table and
+ * result (bit for bit) as ozaki_zgemm; the caller still owns A, B and C.
+ *
+ * Its scratch (exponent codes, packed slices, the int64 carry space of long
+ * contractions) is one fixed device array of OZAKI_NOALLOC_SCRATCH_BYTES per
+ * device, held from the library's load on that device until the process
+ * ends; the call allocates and frees nothing, ignores ozaki_set_workspace and
+ * records no phase timing. A product whose scratch would exceed the array
+ * (ozaki_workspace_bytes('z', m, n, k, slices) > OZAKI_NOALLOC_SCRATCH_BYTES;
+ * e.g. 1024^3 at s = 7 fits, 1536^3 does not) returns OZAKI_ERR_TOO_LARGE
+ * with nothing launched. Every call on one device shares that array, which
+ * keeps the last call's contents (each call rewrites what it reads): calls
+ * that overlap on one device (other streams, other host threads) race.
+ */
+#define OZAKI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ozaki_zgemm_noalloc(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                        ozaki_z alpha, const ozaki_z *A, int64_t lda, const ozaki_z *B,
+                        int64_t ldb, ozaki_z beta, ozaki_z *C, int64_t ldc, int slices);
 
 /*
  * Slice kind of ozaki_dgemm / ozaki_zgemm (and of ozaki_workspace_bytes and

@@ -20,7 +20,7 @@ import os
 
 __all__ = [
     "OzakiError", "OzakiUnavailable", "ozaki_z", "library", "library_path",
-    "ozaki_dgemm", "ozaki_zgemm", "ozaki_native_dgemm", "ozaki_native_zgemm",
+    "ozaki_dgemm", "ozaki_zgemm", "ozaki_zgemm_noalloc", "ozaki_native_dgemm", "ozaki_native_zgemm",
     "ozaki_set_stream", "ozaki_set_workspace", "ozaki_workspace_bytes",
     "ozaki_finalize", "ozaki_status_string", "ozaki_timing_enable", "ozaki_timing_read", "ozaki_debug_exponents",
     "ozaki_debug_split", "ozaki_debug_diagonals", "matmul", "S_MAX", "ozaki_zgemm_batched",
@@ -65,6 +65,8 @@ _SIG = {
                                _i64, _c.c_double, _vp, _i64, _c.c_int]),
     "ozaki_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
                                _i64, ozaki_z, _vp, _i64, _c.c_int]),
+    "ozaki_zgemm_noalloc": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64,
+                                       _vp, _i64, ozaki_z, _vp, _i64, _c.c_int]),
     "ozaki2_dgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, _c.c_double, _vp, _i64, _vp,
                                 _i64, _c.c_double, _vp, _i64, _c.c_int]),
     "ozaki2_zgemm": (_c.c_int, [_c.c_char, _c.c_char, _i64, _i64, _i64, ozaki_z, _vp, _i64, _vp,
@@ -180,6 +182,13 @@ def ozaki_zgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, sl
     _bind_stream()
     return library().ozaki_zgemm(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A), lda,
                                  _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(slices))
+
+
+def ozaki_zgemm_noalloc(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                        slices) -> int:
+    _bind_stream()
+    return library().ozaki_zgemm_noalloc(_ch(transa), _ch(transb), m, n, k, _z(alpha), _ptr(A),
+                                         lda, _ptr(B), ldb, _z(beta), _ptr(C), ldc, int(slices))
 
 
 def ozaki2_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, moduli) -> int:

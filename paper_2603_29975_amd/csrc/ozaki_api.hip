@@ -299,13 +299,14 @@ int check_gemm_args(char transa, char transb, int64_t m, int64_t n, int64_t k, i
 }
 
 // Scan and split both operands into the workspace described by `p`.
-int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t st) {
+int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t st,
+            bool timed = true) {
   int *codeA = reinterpret_cast<int *>(ws + p.off_codeA);
   int *codeB = reinterpret_cast<int *>(ws + p.off_codeB);
   int8_t *SA = reinterpret_cast<int8_t *>(ws + p.off_SA);
   int8_t *SB = reinterpret_cast<int8_t *>(ws + p.off_SB);
   int rc;
-  int mk = phase_begin(OZAKI_PHASE_SCAN, st);
+  int mk = timed ? phase_begin(OZAKI_PHASE_SCAN, st) : -1;
   // codeA and codeB lie back to back (codeB at off_codeB): one fill zeroes both
   if ((rc = hip_rc(launch_fill_i32(codeA, (int64_t)((p.off_codeB - p.off_codeA) / sizeof(int)) + p.n,
                                    0, st))))
@@ -313,7 +314,7 @@ int prepare(const Plan &p, char *ws, const View &va, const View &vb, hipStream_t
   if ((rc = hip_rc(launch_scan(va, p.cplx, codeA, st)))) return rc;
   if ((rc = hip_rc(launch_scan(vb, p.cplx, codeB, st)))) return rc;
   phase_end(mk, st);
-  mk = phase_begin(OZAKI_PHASE_SPLIT, st);
+  mk = timed ? phase_begin(OZAKI_PHASE_SPLIT, st) : -1;
   if ((rc = hip_rc(launch_split(va, p.cplx, false, codeA, p.S, SA, p.nrbQ, p.nkb, st, p.b8))))
     return rc;
   if ((rc = hip_rc(launch_split(vb, p.cplx, true, codeB, p.S, SB, p.nrbP, p.nkb, st, p.b8))))
@@ -359,9 +360,15 @@ GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, dou
   return a;
 }
 
-int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
-                  double ar, double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
-                  double br, double bi, void *C, int64_t ldc, int slices) {
+// One emulated product. fixed_ws == nullptr: scratch from get_workspace and
+// phase timing as enabled; otherwise the scratch is the device memory that
+// fixed_ws provides (called once the arguments have passed their checks;
+// fixed_cap bytes, OZAKI_ERR_TOO_LARGE beyond them) and nothing is allocated
+// or timed.
+int emulated_gemm_ws(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                     double ar, double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                     double br, double bi, void *C, int64_t ldc, int slices,
+                     int (*fixed_ws)(char **), size_t fixed_cap) {
   int rc = check_gemm_args(transa, transb, m, n, k, lda, ldb, ldc);
   if (rc) return rc;
   const bool b8 = split_b8();
@@ -380,19 +387,33 @@ int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int
   int dev = 0;
   if ((rc = current_device(&dev))) return rc;
   const Plan p = make_plan(cplx, m, n, k, slices, g.dev[dev].num_cu, b8);
-  void *wsv = nullptr;
-  if ((rc = get_workspace(p.total, &wsv))) return rc;
-  char *ws = static_cast<char *>(wsv);
+  char *ws = nullptr;
+  if (fixed_ws == nullptr) {
+    void *wsv = nullptr;
+    if ((rc = get_workspace(p.total, &wsv))) return rc;
+    ws = static_cast<char *>(wsv);
+  } else {
+    if (p.total > fixed_cap) return OZAKI_ERR_TOO_LARGE;
+    if ((rc = fixed_ws(&ws))) return rc;
+  }
+  const bool timed = fixed_ws == nullptr;
   const View va = view_opA(A, transa, m, k, lda, cplx);
   const View vb = view_opB(B, transb, k, n, ldb, cplx);
-  if ((rc = prepare(p, ws, va, vb, g.stream))) return rc;
+  if ((rc = prepare(p, ws, va, vb, g.stream, timed))) return rc;
   const GemmArgs ga = gemm_args(p, ws, ar, ai, br, bi, beta_zero, C, ldc, nullptr);
-  const int mk = phase_begin(OZAKI_PHASE_GEMM, g.stream);
+  const int mk = timed ? phase_begin(OZAKI_PHASE_GEMM, g.stream) : -1;
   rc = hip_rc(launch_ozgemm(slices, gemm_config(cplx, slices, m, p.nprime, p.nkb), ga,
                             g.dev[dev].num_cu, g.stream));
   phase_end(mk, g.stream);
-  if (g_tm.on) ++g_tm.calls;
+  if (timed && g_tm.on) ++g_tm.calls;
   return rc;
+}
+
+int emulated_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  double ar, double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                  double br, double bi, void *C, int64_t ldc, int slices) {
+  return emulated_gemm_ws(cplx, transa, transb, m, n, k, ar, ai, A, lda, B, ldb, br, bi, C, ldc,
+                          slices, nullptr, 0);
 }
 
 int native_gemm(bool cplx, char transa, char transb, int64_t m, int64_t n, int64_t k, double ar,
@@ -1490,6 +1511,16 @@ int tune_shape(char kind, int64_t m, int64_t n, int64_t k, int slices, bool *cpl
 
 }  // namespace
 
+namespace oz {
+int zgemm_fixed_scratch(char transa, char transb, int64_t m, int64_t n, int64_t k, double ar,
+                        double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                        double br, double bi, void *C, int64_t ldc, int slices,
+                        int (*scratch)(char **), size_t scratch_bytes) {
+  return emulated_gemm_ws(true, transa, transb, m, n, k, ar, ai, A, lda, B, ldb, br, bi, C, ldc,
+                          slices, scratch, scratch_bytes);
+}
+}  // namespace oz
+
 extern "C" {
 
 int ozaki_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
@@ -1970,6 +2001,7 @@ const char *ozaki_status_string(int status) {
     case OZAKI_ERR_HIP: return "HIP runtime error";
     case OZAKI_ERR_ALLOC: return "device workspace allocation failed";
     case OZAKI_ERR_WORKSPACE: return "caller workspace too small";
+    case OZAKI_ERR_TOO_LARGE: return "product needs more scratch than the fixed device array holds";
     case OZAKI_ERR_NO_DEVICE: return "no usable device";
     case OZAKI_ERR_INTERNAL: return "internal error";
     case OZAKI_ERR_NO_SELECTOR: return "automatic slice selection needs a loaded selector";

@@ -276,4 +276,13 @@ struct NativeArgs {
 };
 hipError_t launch_native(const NativeArgs &a, hipStream_t st);
 
+// One emulated complex product (the ozaki_zgemm path) whose scratch is the
+// device memory of `scratch_bytes` bytes that scratch() provides (called after
+// the argument checks and quick returns): nothing is allocated, phase timing
+// is skipped, OZAKI_ERR_TOO_LARGE when the product needs more.
+int zgemm_fixed_scratch(char transa, char transb, int64_t m, int64_t n, int64_t k, double ar,
+                        double ai, const void *A, int64_t lda, const void *B, int64_t ldb,
+                        double br, double bi, void *C, int64_t ldc, int slices,
+                        int (*scratch)(char **), size_t scratch_bytes);
+
 }  // namespace oz
