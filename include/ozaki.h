@@ -282,8 +282,10 @@ int ozaki_zgemm_batched(const char *transa, const char *transb, const int64_t *m
  */
 int ozaki_load_selector(const float *params, float margin, double target, double kappa);
 
-/* 1 (default): capture and replay HIP graphs in ozaki_zgemm_batched;
- * 0: launch the same kernels directly on every call. */
+/* 1 (default): capture and replay HIP graphs in ozaki_zgemm_batched and in
+ * ozaki_zgetrf / ozaki_zgetri (one graph per argument set, captured on the
+ * first call; not while phase timing is on); 0: launch the same kernels
+ * directly on every call. */
 int ozaki_batched_graphs(int on);
 /* Release every cached batched plan and graph (device memory included). */
 int ozaki_batched_cache_clear(void);
@@ -294,8 +296,10 @@ int ozaki_batched_cache_clear(void);
  * are this library's own.
  * A tuning id below 14 is 2 * tile configuration + tile order (0: down the
  * output rows, 1: along the columns); ids 14 .. 20 are configurations 0 .. 6
- * walking the tiles in groups of 16 tile rows. ozaki_tune_configs() gives
- * their number. Every id computes bit-identical results: only the
+ * walking the tiles in groups of 16 tile rows, ids 21 .. 27 in groups of 8
+ * tile rows with each XCD's workgroups on consecutive tiles.
+ * ozaki_tune_configs() gives their number. Every id computes bit-identical
+ * results: only the
  * workgroup shape, the LDS ring depth and the order in which the persistent
  * workgroups walk the output tiles differ.
  * The table maps (kind, slices, bucket of m, of n' = n or 2n, of the 32-deep

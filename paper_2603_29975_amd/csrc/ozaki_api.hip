@@ -48,6 +48,9 @@ struct State {
 
 State g;
 
+// The LU graphs hold workspace pointers: dropped whenever the workspace moves.
+void clear_lu_graphs();
+
 // Slice kind of ozaki_dgemm / ozaki_zgemm and the debug hooks: set by
 // ozaki_set_split, else OZAKI_SPLIT=b8 in the environment, else trunc-7.
 bool split_b8() {
@@ -139,6 +142,7 @@ int get_workspace(size_t bytes, void **out) {
   int rc = current_device(&dev);
   if (rc) return rc;
   if (g.own_ws_bytes[dev] < bytes) {
+    clear_lu_graphs();
     if (g.own_ws[dev] != nullptr) {
       // hipFree waits for work still using the old buffer.
       if (hipFree(g.own_ws[dev]) != hipSuccess) return OZAKI_ERR_HIP;
@@ -602,6 +606,27 @@ int lu_args(int64_t n, const void *A, int64_t lda, const void *ipiv, int64_t nb,
   if (slices < 0 || slices > max_slices(split_b8())) return -6;
   return 0;
 }
+
+// The launch sequence of a factorization ('F') or an inverse ('I'), run on
+// the library's stream. With graphs on (ozaki_batched_graphs) and phase timing
+// off, the sequence is captured once per argument set into a HIP graph on a
+// private stream and replayed afterwards: a 2048 factorization is some 4,100
+// small dependent launches, and a replayed graph spares their host
+// submission. The workspace of the emulated updates is sized before capture
+// (no allocation inside it); every launch parameter is fixed by the
+// arguments, and the pivots reach later kernels through device memory only.
+struct LuGraph {
+  std::vector<uint8_t> sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+std::list<LuGraph> g_lu_graphs;  // most recent first
+constexpr size_t kLuGraphCache = 4;
+hipStream_t g_lu_cap = nullptr;
+
+template <typename Enqueue>
+int lu_run(char what, int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, ozaki_z *X, int64_t ldx,
+           int64_t nb, int slices, Enqueue enqueue);
 
 // View of op(X) for the debug hooks (see ozaki.h for `side`).
 int debug_view(char kind, char side, char trans, int64_t rows, int64_t L, const void *X,
@@ -1509,6 +1534,73 @@ int tune_shape(char kind, int64_t m, int64_t n, int64_t k, int slices, bool *cpl
   return OZAKI_OK;
 }
 
+template <typename Enqueue>
+int lu_run(char what, int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, ozaki_z *X, int64_t ldx,
+           int64_t nb, int slices, Enqueue enqueue) {
+  if (!g_bat.graphs || g_tm.on) return enqueue(g.stream);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::vector<uint8_t> sig;
+  sig_put(sig, what);
+  sig_put(sig, dev);
+  sig_put(sig, n);
+  sig_put(sig, A);
+  sig_put(sig, lda);
+  sig_put(sig, ipiv);
+  sig_put(sig, X);
+  sig_put(sig, ldx);
+  sig_put(sig, nb);
+  sig_put(sig, slices);
+  sig_put(sig, split_b8());
+  for (auto it = g_lu_graphs.begin(); it != g_lu_graphs.end(); ++it) {
+    if (it->sig == sig) {
+      g_lu_graphs.splice(g_lu_graphs.begin(), g_lu_graphs, it);
+      return hip_rc(hipGraphLaunch(g_lu_graphs.front().exec, g.stream));
+    }
+  }
+  // the largest emulated update of either sequence is at most n x n x nb
+  if (slices > 0) {
+    void *wsv = nullptr;
+    const Plan p = make_plan(true, n, n, std::min(nb, n), slices, g.dev[dev].num_cu, split_b8());
+    if ((rc = get_workspace(p.total, &wsv))) return rc;
+  }
+  if (g_lu_cap == nullptr && hipStreamCreateWithFlags(&g_lu_cap, hipStreamNonBlocking) != hipSuccess)
+    return OZAKI_ERR_HIP;
+  if (hipStreamBeginCapture(g_lu_cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return OZAKI_ERR_HIP;
+  const hipStream_t user = g.stream;
+  g.stream = g_lu_cap;  // the emulated and native updates launch on g.stream
+  const int erc = enqueue(g_lu_cap);
+  g.stream = user;
+  LuGraph lg;
+  lg.sig = std::move(sig);
+  const hipError_t e = hipStreamEndCapture(g_lu_cap, &lg.graph);
+  if (erc != OZAKI_OK || e != hipSuccess ||
+      hipGraphInstantiate(&lg.exec, lg.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    if (lg.exec) (void)hipGraphExecDestroy(lg.exec);
+    if (lg.graph) (void)hipGraphDestroy(lg.graph);
+    return erc != OZAKI_OK ? erc : OZAKI_ERR_HIP;
+  }
+  if (g_lu_graphs.size() >= kLuGraphCache) {
+    LuGraph &old = g_lu_graphs.back();
+    (void)hipGraphExecDestroy(old.exec);
+    (void)hipGraphDestroy(old.graph);
+    g_lu_graphs.pop_back();
+  }
+  g_lu_graphs.push_front(std::move(lg));
+  return hip_rc(hipGraphLaunch(g_lu_graphs.front().exec, g.stream));
+}
+
+void clear_lu_graphs() {
+  for (LuGraph &lg : g_lu_graphs) {
+    (void)hipGraphExecDestroy(lg.exec);
+    (void)hipGraphDestroy(lg.graph);
+  }
+  g_lu_graphs.clear();
+}
+
 }  // namespace
 
 namespace oz {
@@ -1557,30 +1649,34 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
   if (n == 0) return OZAKI_OK;
   int64_t *flag = nullptr;
   if ((rc = lu_workspace(&flag))) return rc;
-  int64_t *pairs = flag + 1;
-  hipStream_t st = g.stream;
   double2 *a = reinterpret_cast<double2 *>(A);
-  if ((rc = hip_rc(launch_set_i64(flag, n, st)))) return rc;
-  for (int64_t j0 = 0; j0 < n; j0 += nb) {
-    const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
-    for (int64_t c = j0; c < j1; ++c)
-      if ((rc = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return rc;
-    if ((rc = hip_rc(launch_lu_scale(a, lda, n, j0, j1, st)))) return rc;
-    if ((rc = hip_rc(launch_swap_pairs(ipiv, j0, j1, n, pairs, st)))) return rc;
-    if ((rc = hip_rc(launch_apply_pairs(a, lda, w, pairs, 0, j0, j1, n, st)))) return rc;
-    if (j1 < n) {
-      // U12 = L11^-1 A12, then A22 -= L21 U12
-      if ((rc = hip_rc(launch_trsm(false, a + j0 + j0 * lda, lda, w, a + j0 + j1 * lda, lda, n - j1,
-                                   st))))
-        return rc;
-      if ((rc = lu_update(slices, n - j1, n - j1, w, a + j1 + j0 * lda, lda, a + j0 + j1 * lda, lda,
-                          a + j1 + j1 * lda, lda)))
-        return rc;
+  auto enqueue = [&](hipStream_t st) -> int {
+    int r;
+    int64_t *pairs = flag + 1;
+    if ((r = hip_rc(launch_set_i64(flag, n, st)))) return r;
+    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+      const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
+      for (int64_t c = j0; c < j1; ++c)
+        if ((r = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return r;
+      if ((r = hip_rc(launch_lu_scale(a, lda, n, j0, j1, st)))) return r;
+      if ((r = hip_rc(launch_swap_pairs(ipiv, j0, j1, n, pairs, st)))) return r;
+      if ((r = hip_rc(launch_apply_pairs(a, lda, w, pairs, 0, j0, j1, n, st)))) return r;
+      if (j1 < n) {
+        // U12 = L11^-1 A12, then A22 -= L21 U12
+        if ((r = hip_rc(launch_trsm(false, a + j0 + j0 * lda, lda, w, a + j0 + j1 * lda, lda,
+                                    n - j1, st))))
+          return r;
+        if ((r = lu_update(slices, n - j1, n - j1, w, a + j1 + j0 * lda, lda, a + j0 + j1 * lda, lda,
+                           a + j1 + j1 * lda, lda)))
+          return r;
+      }
     }
-  }
+    return OZAKI_OK;
+  };
+  if ((rc = lu_run('F', n, A, lda, ipiv, nullptr, 0, nb, slices, enqueue))) return rc;
   int64_t first_zero = n;
-  if (hipMemcpyAsync(&first_zero, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
+  if (hipMemcpyAsync(&first_zero, flag, sizeof(int64_t), hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
+      hipStreamSynchronize(g.stream) != hipSuccess)
     return OZAKI_ERR_HIP;
   return first_zero < n ? OZAKI_ERR_SINGULAR : OZAKI_OK;
 }
@@ -1594,30 +1690,34 @@ int ozaki_zgetri(int64_t n, const ozaki_z *LU, int64_t lda, const int64_t *ipiv,
   if (n == 0) return OZAKI_OK;
   int64_t *flag = nullptr;
   if ((rc = lu_workspace(&flag))) return rc;
-  int64_t *pairs = flag + 1;
-  hipStream_t st = g.stream;
   const double2 *lu = reinterpret_cast<const double2 *>(LU);
   double2 *x = reinterpret_cast<double2 *>(X);
-  // X = P I (the interchanges in blocks of nb, in order), then Y = L^-1 X
-  // (blocks top down), then X = U^-1 Y (bottom up)
-  if ((rc = hip_rc(launch_identity(x, ldx, n, st)))) return rc;
-  for (int64_t i0 = 0; i0 < n; i0 += nb) {
-    const int64_t i1 = std::min(n, i0 + nb);
-    if ((rc = hip_rc(launch_swap_pairs(ipiv, i0, i1, n, pairs, st)))) return rc;
-    if ((rc = hip_rc(launch_apply_pairs(x, ldx, i1 - i0, pairs, 0, n, 0, 0, st)))) return rc;
-  }
-  for (int64_t i0 = 0; i0 < n; i0 += nb) {
-    const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
-    if ((rc = hip_rc(launch_trsm(false, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return rc;
-    if ((rc = lu_update(slices, n - i1, n, w, lu + i1 + i0 * lda, lda, x + i0, ldx, x + i1, ldx)))
-      return rc;
-  }
-  for (int64_t i0 = (n - 1) / nb * nb; i0 >= 0; i0 -= nb) {
-    const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
-    if ((rc = hip_rc(launch_trsm(true, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return rc;
-    if ((rc = lu_update(slices, i0, n, w, lu + i0 * lda, lda, x + i0, ldx, x, ldx))) return rc;
-  }
-  return OZAKI_OK;
+  auto enqueue = [&](hipStream_t st) -> int {
+    int r;
+    int64_t *pairs = flag + 1;
+    // X = P I (the interchanges in blocks of nb, in order), then Y = L^-1 X
+    // (blocks top down), then X = U^-1 Y (bottom up)
+    if ((r = hip_rc(launch_identity(x, ldx, n, st)))) return r;
+    for (int64_t i0 = 0; i0 < n; i0 += nb) {
+      const int64_t i1 = std::min(n, i0 + nb);
+      if ((r = hip_rc(launch_swap_pairs(ipiv, i0, i1, n, pairs, st)))) return r;
+      if ((r = hip_rc(launch_apply_pairs(x, ldx, i1 - i0, pairs, 0, n, 0, 0, st)))) return r;
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += nb) {
+      const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
+      if ((r = hip_rc(launch_trsm(false, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return r;
+      if ((r = lu_update(slices, n - i1, n, w, lu + i1 + i0 * lda, lda, x + i0, ldx, x + i1, ldx)))
+        return r;
+    }
+    for (int64_t i0 = (n - 1) / nb * nb; i0 >= 0; i0 -= nb) {
+      const int64_t i1 = std::min(n, i0 + nb), w = i1 - i0;
+      if ((r = hip_rc(launch_trsm(true, lu + i0 + i0 * lda, lda, w, x + i0, ldx, n, st)))) return r;
+      if ((r = lu_update(slices, i0, n, w, lu + i0 * lda, lda, x + i0, ldx, x, ldx))) return r;
+    }
+    return OZAKI_OK;
+  };
+  return lu_run('I', n, const_cast<ozaki_z *>(LU), lda, const_cast<int64_t *>(ipiv), X, ldx, nb,
+                slices, enqueue);
 }
 
 int ozaki2_moduli(int moduli, int32_t *out) {
@@ -1755,6 +1855,7 @@ int ozaki_batched_graphs(int on) {
   if (want != g_bat.graphs) {
     for (BatchedPlan *pl : g_bat.cache) free_plan(pl);
     g_bat.cache.clear();
+    clear_lu_graphs();
   }
   g_bat.graphs = want;
   return OZAKI_OK;
@@ -1763,6 +1864,7 @@ int ozaki_batched_graphs(int on) {
 int ozaki_batched_cache_clear(void) {
   for (BatchedPlan *pl : g_bat.cache) free_plan(pl);
   g_bat.cache.clear();
+  clear_lu_graphs();
   return OZAKI_OK;
 }
 
@@ -1897,6 +1999,7 @@ int ozaki_set_stream(void *hip_stream) {
 }
 
 int ozaki_set_workspace(void *device_ptr, size_t bytes) {
+  clear_lu_graphs();
   if (device_ptr == nullptr) {
     g.user_ws = nullptr;
     g.user_ws_bytes = 0;
@@ -1961,6 +2064,7 @@ int ozaki_timing_read(double *ms, int64_t *calls) {
 
 int ozaki_finalize(void) {
   int rc = OZAKI_OK;
+  clear_lu_graphs();
   for (int d = 0; d < kMaxDev; ++d) {
     if (g.own_ws[d] != nullptr) {
       int cur = 0;

@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
     // The problem this tile belongs to (uniform across the workgroup, so the
     // descriptor is fetched with scalar loads).
     const GemmProblem a = GROUPED ? G.probs[G.tile_prob[tn]] : G.one;
-    const int64_t local = GROUPED ? (int64_t)G.tile_local[tn] : tn;
+    int64_t local = GROUPED ? (int64_t)G.tile_local[tn] : tn;
+    if (!GROUPED && G.order == 3) local = tile::xcd_major(tn, ntiles);
     int64_t tj, ti;
     tile::tile_coords(local, G.order, a.m, a.nprime, C_::BJ, C_::BI, tj, ti);
     const int64_t nkb = a.nkb;
@@ -254,10 +255,11 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
 //      B' fragment feeds two MFMAs; S <= 6 only (else configuration 2)
 // A tuning id below 14 is 2 * configuration + tile order (0: consecutive
 // tiles walk down the rows i, 1: along the columns j'); ids 14 .. 20 are
-// configurations 0 .. 6 with the grouped tile order 2 (see tile_coords).
+// configurations 0 .. 6 with the grouped tile order 2, ids 21 .. 27 with the
+// XCD-aware order 3 (see tile_coords and xcd_major).
 constexpr int kNumCfg = 7;
-constexpr int id_cfg(int id) { return id < 2 * kNumCfg ? id >> 1 : id - 2 * kNumCfg; }
-constexpr int id_order(int id) { return id < 2 * kNumCfg ? (id & 1) : 2; }
+constexpr int id_cfg(int id) { return id < 2 * kNumCfg ? id >> 1 : (id - 2 * kNumCfg) % kNumCfg; }
+constexpr int id_order(int id) { return id < 2 * kNumCfg ? (id & 1) : 2 + (id - 2 * kNumCfg) / kNumCfg; }
 
 template <int CFG>
 struct Pick;
@@ -324,7 +326,7 @@ constexpr int waves_of() {
 
 int64_t kb_chunk_for(int S, bool b8) { return chunk_blocks(S, b8 ? 128 : 127); }
 
-int gemm_num_configs() { return 3 * kNumCfg; }
+int gemm_num_configs() { return 4 * kNumCfg; }
 
 size_t gemm_flush_bytes(int S, int cfg, int num_cu) {
   // the largest per-workgroup carry space over the configurations, so that a

@@ -204,12 +204,28 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
   }
 }
 
+// Order 3: workgroup w of a persistent grid runs on XCD w % 8 (workgroups are
+// dealt to the 8 XCDs round-robin), and each XCD has its own L2. Within each
+// full round of gridDim.x tiles, tile number tn is given to slot w of the
+// round as xcd_major(tn): the tiles of one XCD's workgroups are consecutive
+// in the grouped order (8 tile rows per group), so they share 8 A' stripes
+// and few B' stripes in that XCD's L2 instead of every XCD fetching all the
+// stripes of the round. A partial last round keeps the identity.
+__device__ __forceinline__ int64_t xcd_major(int64_t tn, int64_t ntiles) {
+  const int64_t G = gridDim.x;
+  if ((G & 7) != 0) return tn;
+  const int64_t r0 = tn - tn % G;
+  if (r0 + G > ntiles) return tn;
+  const int64_t w = tn - r0;
+  return r0 + (w & 7) * (G >> 3) + (w >> 3);
+}
+
 // Output tile (tj, ti) of tile number `local` in a grid of tiles BJ x BI:
 // order 0 walks down the rows i first, order 1 along the columns j' first,
 // order 2 in groups of 16 tile rows, down the rows of a group first (the
 // tiles in flight at once then share 16 A' stripes and few B' stripes, which
 // keeps long contractions in the caches instead of streaming every B' stripe
-// once per round).
+// once per round); order 3 in groups of 8 tile rows (after xcd_major).
 __device__ __forceinline__ void tile_coords(int64_t local, int order, int64_t m, int64_t nprime,
                                             int BJ, int BI, int64_t &tj, int64_t &ti) {
   const int64_t nti = (m + BI - 1) / BI;
@@ -221,7 +237,7 @@ __device__ __forceinline__ void tile_coords(int64_t local, int order, int64_t m,
     ti = local / ntj;
     tj = local % ntj;
   } else {
-    constexpr int64_t kGroup = 16;
+    const int64_t kGroup = order == 2 ? 16 : 8;
     const int64_t ntj = (nprime + BJ - 1) / BJ;
     const int64_t g = local / (kGroup * ntj), r = local - g * (kGroup * ntj);
     const int64_t gh = nti - g * kGroup < kGroup ? nti - g * kGroup : kGroup;

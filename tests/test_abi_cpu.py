@@ -146,7 +146,7 @@ def test_tuning_table_host_logic():
     # The tuning table is host state: set / get / clear work without a GPU.
     assert oz.ozaki_tune_clear() == 0
     nid = oz.ozaki_tune_configs()
-    assert nid == 21                       # 7 tile configurations x 3 tile orders
+    assert nid == 28                       # 7 tile configurations x 4 tile orders
     assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 7) == 0          # default id
     assert oz.ozaki_tune_set("z", 2048, 2048, 2048, 7, nid - 1) == 0
     assert oz.ozaki_tune_get("z", 2048, 2048, 2048, 7) == nid - 1
