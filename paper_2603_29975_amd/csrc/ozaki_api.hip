@@ -782,7 +782,12 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
                const ozaki_z *beta, ozaki_z *const *C, const int64_t *ldc, int64_t batch,
                const int *slices, int num_cu, BatchedPlan *pl, Alloc alloc,
                std::vector<uint8_t> &host, const int *split_slices = nullptr,
-               bool unscaled = false) {
+               bool unscaled = false, int *const *ext_codeA = nullptr,
+               int *const *ext_codeB = nullptr) {
+  // ext_codeA/B (per batch entry): exponent codes already computed; the plan
+  // then has no scan of its own and its split and GEMM read these
+  const bool ext = ext_codeA != nullptr && ext_codeB != nullptr;
+  std::vector<int64_t> prob_b;
   pl->used.assign((size_t)batch, 0);
   pl->tune_id = batched_tune_id();
   std::vector<GemmProblem> probs;
@@ -821,8 +826,11 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
     probs.push_back(gp);
     const View va = view_opA(A[b], transa[b], m[b], k[b], lda[b], true);
     const View vb = view_opB(B[b], transb[b], k[b], n[b], ldb[b], true);
-    scans.push_back({va, nullptr, 1, va.sr == 1 ? 1 : 0});
-    scans.push_back({vb, nullptr, 1, vb.sr == 1 ? 1 : 0});
+    prob_b.push_back(b);
+    if (!ext) {
+      scans.push_back({va, nullptr, 1, va.sr == 1 ? 1 : 0});
+      scans.push_back({vb, nullptr, 1, vb.sr == 1 ? 1 : 0});
+    }
     splits.push_back({va, nullptr, nullptr, p.nrbQ, p.nkb, S_split, 1, 0});
     splits.push_back({vb, nullptr, nullptr, p.nrbP, p.nkb, S_split, 1, 1});
   }
@@ -880,13 +888,17 @@ int build_plan(const char *transa, const char *transb, const int64_t *m, const i
     GemmProblem &gp = probs[i];
     gp.SP = reinterpret_cast<const int8_t *>(w + p.off_SB);
     gp.SQ = reinterpret_cast<const int8_t *>(w + p.off_SA);
-    gp.codeA = reinterpret_cast<const int *>(w + p.off_codeA);
-    gp.codeB = reinterpret_cast<const int *>(w + p.off_codeB);
-    scans[2 * i].code = reinterpret_cast<int *>(w + p.off_codeA);
-    scans[2 * i + 1].code = reinterpret_cast<int *>(w + p.off_codeB);
-    splits[2 * i].code = reinterpret_cast<const int *>(w + p.off_codeA);
+    int *ca = ext ? ext_codeA[prob_b[i]] : reinterpret_cast<int *>(w + p.off_codeA);
+    int *cb = ext ? ext_codeB[prob_b[i]] : reinterpret_cast<int *>(w + p.off_codeB);
+    gp.codeA = ca;
+    gp.codeB = cb;
+    if (!ext) {
+      scans[2 * i].code = ca;
+      scans[2 * i + 1].code = cb;
+    }
+    splits[2 * i].code = ca;
     splits[2 * i].out = reinterpret_cast<int8_t *>(w + p.off_SA);
-    splits[2 * i + 1].code = reinterpret_cast<const int *>(w + p.off_codeB);
+    splits[2 * i + 1].code = cb;
     splits[2 * i + 1].out = reinterpret_cast<int8_t *>(w + p.off_SB);
   }
   host.assign(desc_bytes, 0);
@@ -1248,8 +1260,11 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     std::vector<const ozaki_z *> pa(np), pb(np);
     std::vector<ozaki_z *> pc(np);
     std::vector<int> sl(np), cap(np);
+    std::vector<int *> eca(np), ecb(np);  // the feature scan's codes: no second scan
     for (size_t x = 0; x < np; ++x) {
       const int64_t e = pending[x], b = E[e];
+      eca[x] = reinterpret_cast<int *>(ws + o_codeA[e]);
+      ecb[x] = reinterpret_cast<int *>(ws + o_codeB[e]);
       ta[x] = transa[b];
       tb[x] = transb[b];
       mm[x] = m[b];
@@ -1274,7 +1289,7 @@ int auto_batched(const char *transa, const char *transb, const int64_t *m, const
     if ((rc = build_plan(ta.data(), tb.data(), mm.data(), nn.data(), kk.data(), one.data(), pa.data(),
                          la.data(), pb.data(), lb.data(), zero.data(), pc.data(), lc.data(),
                          (int64_t)np, sl.data(), g.dev[dev].num_cu, &rp, sel_plan_memory, host,
-                         cap.data(), true)))
+                         cap.data(), true, eca.data(), ecb.data())))
       return rc;
     if ((rc = hip_rc(hipMemcpyAsync(rp.mem, host.data(), host.size(), hipMemcpyHostToDevice, st))))
       return rc;
