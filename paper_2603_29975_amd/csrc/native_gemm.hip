@@ -23,7 +23,11 @@
 // launch bounds ask for two workgroups per CU (<= 256 registers per wave):
 // left free, the compiler takes 334 (accumulators in AGPRs), which allows one
 // wave per SIMD and exposes every LDS and barrier wait (16384^3 complex: 26.6
-// TFLOP/s at one wave per SIMD, 43.1 at two).
+// TFLOP/s at one wave per SIMD, 43.1 at two). The prefetch loads are
+// unconditional (an element outside the matrix reads element (0, 0) and is
+// replaced by zero when stored to LDS), so they stay in flight under the
+// stage's MFMAs: with a bounds test around each load the compiler waited for
+// every load before the MFMAs (43.1 -> 64.3 TFLOP/s at 16384^3).
 #include "ozaki_internal.hpp"
 
 namespace oz {
@@ -45,20 +49,17 @@ struct Loader {
   using T = typename std::conditional<CPLX, double2, double>::type;
 };
 
+// Raw element (r, l) of the view, or element (0, 0) when (r, l) lies outside
+// it (ok = false; the caller substitutes zero). The load is unconditional, so
+// the loads of a stage go out together and nothing waits for them before the
+// stage's MFMAs; the conjugation is applied where the element is stored.
 template <bool CPLX>
-__device__ __forceinline__ typename Loader<CPLX>::T load_elem(const View &v, int64_t r, int64_t l) {
+__device__ __forceinline__ typename Loader<CPLX>::T load_raw(const View &v, int64_t r, int64_t l,
+                                                             bool &ok) {
   using T = typename Loader<CPLX>::T;
-  if (r < v.R && l < v.L) {
-    T x = reinterpret_cast<const T *>(v.base)[r * v.sr + l * v.sl];
-    if constexpr (CPLX) {
-      if (v.conj) x.y = -x.y;
-    }
-    return x;
-  }
-  if constexpr (CPLX)
-    return make_double2(0.0, 0.0);
-  else
-    return 0.0;
+  ok = r < v.R && l < v.L;
+  const int64_t off = ok ? r * v.sr + l * v.sl : 0;
+  return reinterpret_cast<const T *>(v.base)[off];
 }
 
 template <bool CPLX>
@@ -93,6 +94,8 @@ __global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
 
   T pbuf[LD::PCNT];
   T qbuf[LD::QCNT];
+  bool pok[LD::PCNT], qok[LD::QCNT];
+  const bool pconj = CPLX && a.B.conj, qconj = CPLX && a.A.conj;
 
   auto fetch = [&](int64_t st) {
     const int64_t l0 = st * PL;
@@ -101,14 +104,14 @@ __global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
       const int e = tid + x * NTH;
       const int rl = p_rows_fast ? e % PR : e / PL;
       const int ll = p_rows_fast ? e / PR : e % PL;
-      pbuf[x] = load_elem<CPLX>(a.B, pr0 + rl, l0 + ll);
+      pbuf[x] = load_raw<CPLX>(a.B, pr0 + rl, l0 + ll, pok[x]);
     }
 #pragma unroll
     for (int x = 0; x < LD::QCNT; ++x) {
       const int e = tid + x * NTH;
       const int rl = q_rows_fast ? e % QR : e / QL;
       const int ll = q_rows_fast ? e / QR : e % QL;
-      qbuf[x] = load_elem<CPLX>(a.A, i0 + rl, l0 + ll);
+      qbuf[x] = load_raw<CPLX>(a.A, i0 + rl, l0 + ll, qok[x]);
     }
   };
   auto deposit = [&](int buf) {
@@ -120,7 +123,8 @@ __global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
       const int rl = p_rows_fast ? e % PR : e / PL;
       const int ll = p_rows_fast ? e / PR : e % PL;
       if constexpr (CPLX) {
-        const double2 z = pbuf[x];
+        double2 z = pok[x] ? pbuf[x] : make_double2(0.0, 0.0);
+        if (pconj) z.y = -z.y;
         const int rre = 16 * (rl >> 3) + (rl & 7);  // real-part row of column rl
         const int rim = rre + 8;                    // imaginary-part row
         P[(2 * ll) * LDJ + rre] = z.x;
@@ -128,7 +132,7 @@ __global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
         P[(2 * ll) * LDJ + rim] = z.y;
         P[(2 * ll + 1) * LDJ + rim] = z.x;
       } else {
-        P[ll * LDJ + rl] = pbuf[x];
+        P[ll * LDJ + rl] = pok[x] ? pbuf[x] : 0.0;
       }
     }
 #pragma unroll
@@ -137,11 +141,12 @@ __global__ void __launch_bounds__(NTH, 2) k_native(NativeArgs a) {
       const int rl = q_rows_fast ? e % QR : e / QL;
       const int ll = q_rows_fast ? e / QR : e % QL;
       if constexpr (CPLX) {
-        const double2 z = qbuf[x];
+        double2 z = qok[x] ? qbuf[x] : make_double2(0.0, 0.0);
+        if (qconj) z.y = -z.y;
         Q[(2 * ll) * LDI + rl] = z.x;
         Q[(2 * ll + 1) * LDI + rl] = z.y;
       } else {
-        Q[ll * LDI + rl] = qbuf[x];
+        Q[ll * LDI + rl] = qok[x] ? qbuf[x] : 0.0;
       }
     }
   };
