@@ -597,6 +597,20 @@ int lu_workspace(int64_t **out) {
   return OZAKI_OK;
 }
 
+// How ozaki_zgetrf factors its panels: OZAKI_LU_PANEL=columns (one pivot and
+// one update launch per column), leaf8 / leaf4 / leaf2 (that leaf width
+// wherever its rows fit, else columns), anything else the widest leaf that
+// fits. Read at every call; all modes give the same factors bit for bit.
+int lu_panel_mode() {
+  const char *e = getenv("OZAKI_LU_PANEL");
+  if (e == nullptr) return kLuPanelAuto;
+  if (std::strcmp(e, "columns") == 0) return kLuPanelColumns;
+  if (std::strcmp(e, "leaf8") == 0) return kLuPanelLeaf8;
+  if (std::strcmp(e, "leaf4") == 0) return kLuPanelLeaf4;
+  if (std::strcmp(e, "leaf2") == 0) return kLuPanelLeaf2;
+  return kLuPanelAuto;
+}
+
 int lu_args(int64_t n, const void *A, int64_t lda, const void *ipiv, int64_t nb, int slices) {
   if (n < 0) return -1;
   if (A == nullptr && n > 0) return -2;
@@ -1665,15 +1679,14 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
   int64_t *flag = nullptr;
   if ((rc = lu_workspace(&flag))) return rc;
   double2 *a = reinterpret_cast<double2 *>(A);
+  const int mode = lu_panel_mode();
   auto enqueue = [&](hipStream_t st) -> int {
     int r;
     int64_t *pairs = flag + 1;
     if ((r = hip_rc(launch_set_i64(flag, n, st)))) return r;
     for (int64_t j0 = 0; j0 < n; j0 += nb) {
       const int64_t j1 = std::min(n, j0 + nb), w = j1 - j0;
-      for (int64_t c = j0; c < j1; ++c)
-        if ((r = hip_rc(launch_lu_column(a, lda, n, c, j0, j1, ipiv, flag, st)))) return r;
-      if ((r = hip_rc(launch_lu_scale(a, lda, n, j0, j1, st)))) return r;
+      if ((r = hip_rc(launch_lu_panel(a, lda, n, j0, j1, ipiv, flag, mode, st)))) return r;
       if ((r = hip_rc(launch_swap_pairs(ipiv, j0, j1, n, pairs, st)))) return r;
       if ((r = hip_rc(launch_apply_pairs(a, lda, w, pairs, 0, j0, j1, n, st)))) return r;
       if (j1 < n) {
@@ -1688,7 +1701,7 @@ int ozaki_zgetrf(int64_t n, ozaki_z *A, int64_t lda, int64_t *ipiv, int64_t nb, 
     }
     return OZAKI_OK;
   };
-  if ((rc = lu_run('F', n, A, lda, ipiv, nullptr, 0, nb, slices, enqueue))) return rc;
+  if ((rc = lu_run((char)('a' + mode), n, A, lda, ipiv, nullptr, 0, nb, slices, enqueue))) return rc;
   int64_t first_zero = n;
   if (hipMemcpyAsync(&first_zero, flag, sizeof(int64_t), hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
       hipStreamSynchronize(g.stream) != hipSuccess)

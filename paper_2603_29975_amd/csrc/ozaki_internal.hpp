@@ -253,6 +253,16 @@ constexpr int64_t kLuMaxBlock = 1024;  // panel / block width limit (one thread 
 hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64_t p0, int64_t p1,
                             int64_t *ipiv, int64_t *singular, hipStream_t st);
 hipError_t launch_lu_scale(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, hipStream_t st);
+// The columns of the panel [p0, p1), multipliers included: leaves of up to 8
+// columns factored in registers by one workgroup (k_lu_leaf, which stores the
+// multipliers), each followed by the leaf's interchanges and updates on the
+// other panel columns (k_lu_trail); a column whose rows do not fit a leaf goes
+// through launch_lu_column and is scaled by launch_lu_scale at the end. The
+// mode picks the leaf widths (automatic: the widest that fits) or forces one
+// width, or columns only; every mode gives the same factors bit for bit.
+enum { kLuPanelAuto = 0, kLuPanelColumns = 1, kLuPanelLeaf8 = 2, kLuPanelLeaf4 = 3, kLuPanelLeaf2 = 4 };
+hipError_t launch_lu_panel(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, int64_t *ipiv,
+                           int64_t *singular, int mode, hipStream_t st);
 constexpr int64_t kLuPairWords = 4 * kLuMaxBlock;
 hipError_t launch_swap_pairs(const int64_t *ipiv, int64_t c0, int64_t c1, int64_t n,
                              int64_t *pairs, hipStream_t st);

@@ -37,11 +37,11 @@ __device__ __forceinline__ double cabs1(Z a) { return add_rn(fabs(a.re), fabs(a.
 
 // Pivot order: the larger |Re| + |Im| wins, a NaN counts as larger than any
 // number, and equal values (or two NaNs) go to the lower row.
+// Written without branches (bitwise on the comparisons), so a reduction
+// over it stays straight-line code.
 __device__ __forceinline__ bool beats(double v, int64_t i, double bv, int64_t bi) {
-  const bool vn = v != v, bn = bv != bv;
-  if (vn != bn) return vn;
-  if (vn) return i < bi;
-  return v > bv || (v == bv && i < bi);
+  const bool vn = v != v, bn = bv != bv, lower = i < bi;
+  return (vn & !bn) | ((vn == bn) & ((vn & lower) | (v > bv) | ((v == bv) & lower)));
 }
 
 // Pivot of column c (rows c..n-1), then the swap of rows c and the pivot row
@@ -151,6 +151,296 @@ __global__ void __launch_bounds__(256) k_panel_scale(double2 *A, int64_t lda, in
   const int64_t i = p0 + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i <= c || i >= n) return;
   st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
+}
+
+// A leaf of the panel: the columns [c0, c1) (at most L) over the rows [c0, n),
+// factored by one workgroup with every entry in registers (thread t holds rows
+// c0 + t + 512 j, j < RPT, of each leaf column), so the L dependent steps cost
+// one barrier each instead of two kernel launches. Step c:
+//   pivot: each wave reduces its rows with shuffles; the lane holding the
+//     wave's best row copies that row of the leaf to LDS (and lane c - c0,
+//     which holds row c, copies row c); after the barrier every thread reduces
+//     the 8 wave results itself and reads the pivot row from its wave's slot;
+//   interchange of rows c and the pivot row within the leaf columns;
+//   update a_ik -= l_ic a_ck of rows i > c, leaf columns k > c, with the
+//     multiplier l_ic = a_ic / a_cc, which replaces a_ic.
+// These are k_pivot_swap's, k_panel_update's and k_panel_scale's operations on
+// the leaf columns (the multiplier is the same quotient whether taken at step
+// c or at the end of the panel: column c is only permuted after step c), so
+// the leaf ends bit for bit as it would under them; the other panel columns
+// take the leaf's interchanges and updates in k_lu_trail. A
+// leaf narrower than L carries zero columns up to L: they are updated like
+// the others (straight-line code, no per-column tests) but never read by a
+// pivot search and never stored. The LDS slots alternate between even and odd
+// steps, so a thread one step ahead never overwrites a slot still being read.
+constexpr int kLeafThreads = 512;
+
+template <int RPT, int L>
+__global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t lda, int64_t n,
+                                                          int64_t c0, int64_t c1, int64_t *ipiv,
+                                                          int64_t *singular) {
+  constexpr int NT = kLeafThreads, NW = NT / 64;
+  __shared__ double2 srow[2][NW][L];
+  __shared__ double2 sc[2][L];
+  __shared__ double sv[2][NW];
+  __shared__ int64_t si[2][NW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int w = (int)(c1 - c0);
+  Z x[RPT][L];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int64_t i = c0 + t + (int64_t)NT * j;
+#pragma unroll
+    for (int k = 0; k < L; ++k) x[j][k] = (i < n && k < w) ? ld(A + i + (c0 + k) * lda) : Z{0.0, 0.0};
+  }
+  int64_t pivs[L];
+  int first_zero = -1;
+#pragma unroll
+  for (int cc = 0; cc < L; ++cc) {
+    if (cc >= w) break;
+    const int b = cc & 1;
+    const int64_t c = c0 + cc;
+    double best = -1.0;
+    int64_t bi = n;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {  // a thread's rows in increasing order
+      const int64_t i = c0 + t + (int64_t)NT * j;
+      const bool take = i >= c && i < n && beats(cabs1(x[j][cc]), i, best, bi);
+      best = take ? cabs1(x[j][cc]) : best;
+      bi = take ? i : bi;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int64_t oi = __shfl_xor(bi, o);
+      const bool take = beats(ov, oi, best, bi);
+      best = take ? ov : best;
+      bi = take ? oi : bi;
+    }
+    if (bi < n && ((bi - c0) & (NT - 1)) == t) {
+      const int jb = (int)((bi - c0) / NT);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j)
+        if (j == jb)
+#pragma unroll
+          for (int k = 0; k < L; ++k) srow[b][wave][k] = make_double2(x[j][k].re, x[j][k].im);
+    }
+    if (lane == 0) {
+      sv[b][wave] = best;
+      si[b][wave] = bi;
+    }
+    if (t == cc)  // row c = c0 + cc is thread cc's first row
+#pragma unroll
+      for (int k = 0; k < L; ++k) sc[b][k] = make_double2(x[0][k].re, x[0][k].im);
+    __syncthreads();
+    double cv[NW];
+    int64_t ci[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {  // all reads first, then the reduction
+      cv[v] = sv[b][v];
+      ci[v] = si[b][v];
+    }
+    best = cv[0];
+    bi = ci[0];
+    int win = 0;
+#pragma unroll
+    for (int v = 1; v < NW; ++v) {
+      const bool take = beats(cv[v], ci[v], best, bi);
+      best = take ? cv[v] : best;
+      bi = take ? ci[v] : bi;
+      win = take ? v : win;
+    }
+    // row c takes part, so the pivot is a row of [c, n); the pivots go out
+    // after the last step (a store in flight would hold up the next barrier)
+    const int64_t piv = bi;
+    pivs[cc] = piv;
+    if (!(best > 0.0) && first_zero < 0) first_zero = cc;
+    Z pr[L];  // the pivot row: row c after the interchange
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const double2 v = srow[b][win][k];
+      pr[k] = Z{v.x, v.y};
+    }
+    if (piv != c) {
+      if (t == cc)
+#pragma unroll
+        for (int k = 0; k < L; ++k) x[0][k] = pr[k];
+      if (((piv - c0) & (NT - 1)) == t) {
+        const int jp = (int)((piv - c0) / NT);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+          if (j == jp)
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+              const double2 v = sc[b][k];
+              x[j][k] = Z{v.x, v.y};
+            }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int64_t i = c0 + t + (int64_t)NT * j;
+      if (i > c && i < n) {
+        const Z l = zdiv(x[j][cc], pr[cc]);
+        x[j][cc] = l;  // the multiplier, final up to later interchanges
+#pragma unroll
+        for (int k = cc + 1; k < L; ++k) x[j][k] = zsub(x[j][k], zmul(l, pr[k]));
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int64_t i = c0 + t + (int64_t)NT * j;
+    if (i < n)
+#pragma unroll
+      for (int k = 0; k < L; ++k)
+        if (k < w) st(A + i + (c0 + k) * lda, x[j][k]);
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int cc = 0; cc < L; ++cc)
+      if (cc < w) ipiv[c0 + cc] = pivs[cc];
+    if (first_zero >= 0)
+      atomicMin(reinterpret_cast<unsigned long long *>(singular), (unsigned long long)(c0 + first_zero));
+  }
+}
+
+// The other panel columns after the leaf [c0, c1) (w = c1 - c0 <= L), one
+// workgroup per column k: k in [p0, c0) takes the leaf's interchanges only; k
+// in [c1, p1) takes them and then the leaf's steps c = c0 .. c1-1 in order,
+// a_ik -= l_ic a_ck for rows i > c with the multipliers the leaf stored, as
+// k_pivot_swap and k_panel_update would have applied them one column at a
+// time. Exchanging all rows first and updating afterwards gives the same
+// entries: every row exchanged at step c is below every earlier pivot row, so
+// both take each earlier step's update with the multiplier that moves with
+// them. The interchanges touch at most 2 w rows ("slots": rows c0 .. c1-1,
+// then each pivot row below c1 once); thread s < 2w finds which slot's entry
+// ends in slot s by running the exchanges backwards on the slot index, so the
+// exchange is one gather. Rows c0 .. c1-1 then form a chain of w dependent
+// steps, run by the first w lanes of wave 0 with shuffles; each row below c1
+// subtracts its w terms in the order of c.
+constexpr int kTrailThreads = 512, kTrailRows = 4;
+
+template <int L>
+__global__ void __launch_bounds__(kTrailThreads) k_lu_trail(double2 *A, int64_t lda, int64_t n, int64_t c0,
+                                                  int64_t c1, int64_t p0, const int64_t *ipiv) {
+  __shared__ double2 lm[L][L];  // leaf multipliers l_rc, r > c
+  __shared__ double2 u[L];
+  const int t = threadIdx.x;
+  const int w = (int)(c1 - c0);
+  const int64_t b = blockIdx.x;
+  const bool left = b < c0 - p0;
+  const int64_t k = left ? p0 + b : c1 + (b - (c0 - p0));
+  double2 *col = A + k * lda;
+  // every thread reads the w pivots (an entry outside [c, n) is no exchange)
+  int64_t pv[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const int64_t p = q < w ? ipiv[c0 + q] : c0 + q;
+    pv[q] = (p < c0 + q || p >= n) ? c0 + q : p;
+  }
+  if (!left && t < w * w) {
+    const int r = t % w, q = t / w;
+    if (r > q) lm[r][q] = A[c0 + r + (c0 + q) * lda];
+  }
+  // slot of each exchange's pivot row: p - c0 inside the leaf, else w + the
+  // number of distinct pivot rows below c1 named before it first is
+  int ps[L];
+  int m = w;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    int s = q;
+    if (q < w) {
+      if (pv[q] < c1) {
+        s = (int)(pv[q] - c0);
+      } else {
+        int first = q, rank = 0;
+#pragma unroll
+        for (int e = 0; e < L; ++e)
+          if (e < q && pv[e] == pv[q] && e < first) first = e;
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+          bool newrow = e < first && pv[e] >= c1;
+#pragma unroll
+          for (int f = 0; f < L; ++f)
+            if (f < e && pv[f] == pv[e]) newrow = false;
+          rank += newrow ? 1 : 0;
+        }
+        s = w + rank;
+        if (first == q) ++m;
+      }
+    }
+    ps[q] = s;
+  }
+  // thread t < m: the row of slot t and the slot whose entry ends there
+  Z val{0.0, 0.0};
+  int64_t row = 0;
+  if (t < m) {
+    if (t < w) {
+      row = c0 + t;
+    } else {
+#pragma unroll
+      for (int q = 0; q < L; ++q)
+        if (q < w && ps[q] == t) row = pv[q];
+    }
+    int src = t;
+#pragma unroll
+    for (int q = L - 1; q >= 0; --q)
+      if (q < w) src = src == q ? ps[q] : (src == ps[q] ? q : src);
+    int64_t srow = c0 + src;
+    if (src >= w)
+#pragma unroll
+      for (int q = 0; q < L; ++q)
+        if (q < w && ps[q] == src) srow = pv[q];
+    val = ld(col + srow);
+  }
+  __syncthreads();  // every slot read before any is overwritten
+  if (left) {
+    if (t < m) st(col + row, val);
+    return;
+  }
+  if (t >= w && t < m) st(col + row, val);
+  if (t < 64) {
+    Z xr = val;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      if (q >= w) break;
+      const double ure = __shfl(xr.re, q), uim = __shfl(xr.im, q);
+      if (t > q && t < w) {
+        const double2 l = lm[t][q];
+        xr = zsub(xr, zmul(Z{l.x, l.y}, Z{ure, uim}));
+      }
+    }
+    if (t < w) {
+      u[t] = make_double2(xr.re, xr.im);
+      st(col + c0 + t, xr);
+    }
+  }
+  __syncthreads();
+  // kTrailRows rows per thread per pass, every load of a pass issued before
+  // any use (a row past n reads row n - 1 and stores nothing)
+  for (int64_t i0 = c1 + t; i0 < n; i0 += kTrailRows * kTrailThreads) {
+    Z a[kTrailRows][L], y[kTrailRows];
+#pragma unroll
+    for (int h = 0; h < kTrailRows; ++h) {
+      const int64_t i = std::min<int64_t>(i0 + h * kTrailThreads, n - 1);
+#pragma unroll
+      for (int q = 0; q < L; ++q)
+        if (q < w) a[h][q] = ld(A + i + (c0 + q) * lda);
+      y[h] = ld(col + i);
+    }
+#pragma unroll
+    for (int h = 0; h < kTrailRows; ++h) {
+      const int64_t i = i0 + h * kTrailThreads;
+#pragma unroll
+      for (int q = 0; q < L; ++q)
+        if (q < w) {
+          const double2 uq = u[q];
+          y[h] = zsub(y[h], zmul(a[h][q], Z{uq.x, uq.y}));
+        }
+      if (i < n) st(col + i, y[h]);
+    }
+  }
 }
 
 // The row interchanges ipiv[c0..c1) (rows c and ipiv[c] exchanged for c =
@@ -333,6 +623,58 @@ hipError_t launch_lu_column(double2 *A, int64_t lda, int64_t n, int64_t c, int64
     hipLaunchKernelGGL(k_panel_update, dim3(blocks(n - c - 1), (unsigned)(p1 - c - 1)), dim3(256), 0, st,
                        A, lda, n, c);
   return hipGetLastError();
+}
+
+static int lu_leaf_width(int64_t rows, int mode) {
+  // the widest leaf whose rows fit in registers: 512 threads x RPT rows
+  if (mode == kLuPanelColumns) return 0;
+  if (mode == kLuPanelLeaf8 || mode == kLuPanelAuto) {
+    if (rows <= 2048) return 8;
+    if (mode == kLuPanelLeaf8) return 0;
+  }
+  if (mode == kLuPanelLeaf4 || mode == kLuPanelAuto) {
+    if (rows <= 4096) return 4;
+    if (mode == kLuPanelLeaf4) return 0;
+  }
+  return rows <= 8192 ? 2 : 0;
+}
+
+hipError_t launch_lu_panel(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, int64_t *ipiv,
+                           int64_t *singular, int mode, hipStream_t st) {
+  // the rows below a column only shrink, so the columns taken one at a time
+  // (rows that do not fit a leaf) are a prefix [p0, pc) of the panel
+  int64_t c0 = p0, pc = p0;
+  while (c0 < p1) {
+    const int L = lu_leaf_width(n - c0, mode);
+    if (L == 0) {
+      const hipError_t e = launch_lu_column(A, lda, n, c0, p0, p1, ipiv, singular, st);
+      if (e != hipSuccess) return e;
+      pc = ++c0;
+      continue;
+    }
+    const int64_t c1 = std::min(p1, c0 + L);
+    const dim3 lb(kLeafThreads);
+    switch (L) {
+      case 8: hipLaunchKernelGGL((k_lu_leaf<4, 8>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
+      case 4: hipLaunchKernelGGL((k_lu_leaf<8, 4>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
+      default: hipLaunchKernelGGL((k_lu_leaf<16, 2>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
+    }
+    const int64_t cols = (c0 - p0) + (p1 - c1);
+    if (cols > 0) {
+      const dim3 g((unsigned)cols), tb(kTrailThreads);
+      switch (L) {
+        case 8: hipLaunchKernelGGL(k_lu_trail<8>, g, tb, 0, st, A, lda, n, c0, c1, p0, ipiv); break;
+        case 4: hipLaunchKernelGGL(k_lu_trail<4>, g, tb, 0, st, A, lda, n, c0, c1, p0, ipiv); break;
+        default: hipLaunchKernelGGL(k_lu_trail<2>, g, tb, 0, st, A, lda, n, c0, c1, p0, ipiv); break;
+      }
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    c0 = c1;
+  }
+  // the leaves stored their multipliers; the prefix's columns still hold the
+  // unscaled entries
+  return launch_lu_scale(A, lda, n, p0, pc, st);
 }
 
 hipError_t launch_lu_scale(double2 *A, int64_t lda, int64_t n, int64_t p0, int64_t p1, hipStream_t st) {

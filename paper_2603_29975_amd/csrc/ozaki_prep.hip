@@ -50,7 +50,16 @@ __device__ __forceinline__ void scan_rowsfast_block(const View &v, int64_t rb, i
   const int64_t r = rb * 64 + (tid & 63);
   int c = 0;
   if (r < v.R) {
-    for (int64_t l = l0 + (tid >> 6); l < l1; l += 4) c = max(c, elem_code<CPLX>(v.base, r + l * v.sl));
+    // four loads in flight per pass, then the remainder
+    int64_t l = l0 + (tid >> 6);
+    for (; l + 12 < l1; l += 16) {
+      const int a0 = elem_code<CPLX>(v.base, r + l * v.sl);
+      const int a1 = elem_code<CPLX>(v.base, r + (l + 4) * v.sl);
+      const int a2 = elem_code<CPLX>(v.base, r + (l + 8) * v.sl);
+      const int a3 = elem_code<CPLX>(v.base, r + (l + 12) * v.sl);
+      c = max(c, max(max(a0, a1), max(a2, a3)));
+    }
+    for (; l < l1; l += 4) c = max(c, elem_code<CPLX>(v.base, r + l * v.sl));
   }
   __shared__ int red[256];
   red[tid] = c;
@@ -81,7 +90,15 @@ __device__ __forceinline__ void scan_rowcontig_block(const View &v, int64_t rb, 
   const int64_t r = rb * 4 + (threadIdx.x >> 6);
   if (r >= v.R) return;
   int c = 0;
-  for (int64_t l = l0 + lane; l < l1; l += 64) c = max(c, elem_code<CPLX>(v.base, r * v.sr + l));
+  int64_t l = l0 + lane;
+  for (; l + 192 < l1; l += 256) {  // four loads in flight per pass
+    const int a0 = elem_code<CPLX>(v.base, r * v.sr + l);
+    const int a1 = elem_code<CPLX>(v.base, r * v.sr + l + 64);
+    const int a2 = elem_code<CPLX>(v.base, r * v.sr + l + 128);
+    const int a3 = elem_code<CPLX>(v.base, r * v.sr + l + 192);
+    c = max(c, max(max(a0, a1), max(a2, a3)));
+  }
+  for (; l < l1; l += 64) c = max(c, elem_code<CPLX>(v.base, r * v.sr + l));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off));
   if (lane == 0) {
@@ -144,21 +161,34 @@ constexpr int kSplitTileDoubles = 64 * 33 * 2;  // the largest tile (complex, 64
 // consecutive threads on consecutive elements of a row (coalesced), and the
 // threads take their values from there. Rows or elements outside the view
 // are stored as zeros.
+// Every load is issued before the first store to LDS (an element outside the
+// view reads element (0, 0) and is stored as zero), so a thread's loads are in
+// flight together.
 template <bool CPLX, bool SIDEB>
 __device__ __forceinline__ void load_split_tile(const View &v, int64_t bx, int64_t by, double *tile) {
   using T = SplitTile<CPLX, SIDEB>;
+  using E = typename std::conditional<CPLX, double2, double>::type;
+  constexpr int IT = T::TR * T::TL / 256;
+  static_assert(T::TR * T::TL % 256 == 0, "whole passes");
   const int64_t r0 = bx * T::TR, l0 = by * T::TL;
-  for (int c = threadIdx.x; c < T::TR * T::TL; c += 256) {
+  E val[IT];
+  bool in[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int c = threadIdx.x + 256 * it;
+    const int64_t r = r0 + c / T::TL, l = l0 + c % T::TL;
+    in[it] = r < v.R && l < v.L;
+    val[it] = reinterpret_cast<const E *>(v.base)[in[it] ? r * v.sr + l : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int c = threadIdx.x + 256 * it;
     const int rr = c / T::TL, ll = c % T::TL;
-    const int64_t r = r0 + rr, l = l0 + ll;
-    const bool in = r < v.R && l < v.L;
-    if (CPLX) {
-      double2 z = make_double2(0.0, 0.0);
-      if (in) z = reinterpret_cast<const double2 *>(v.base)[r * v.sr + l];
-      *reinterpret_cast<double2 *>(tile + rr * T::PITCH + ll * 2) = z;
-    } else {
-      tile[rr * T::PITCH + ll] = in ? reinterpret_cast<const double *>(v.base)[r * v.sr + l] : 0.0;
-    }
+    if constexpr (CPLX)
+      *reinterpret_cast<double2 *>(tile + rr * T::PITCH + ll * 2) =
+          in[it] ? val[it] : make_double2(0.0, 0.0);
+    else
+      tile[rr * T::PITCH + ll] = in[it] ? val[it] : 0.0;
   }
   __syncthreads();
 }
@@ -180,22 +210,27 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
   Sig sg[16];
   if (CPLX) {
     const double2 *X = reinterpret_cast<const double2 *>(v.base);
+    // every load of the thread is issued before any is used (an entry outside
+    // the view reads element (0, 0), or its zero in the staged tile, and
+    // counts as zero)
+    double2 zs[8];
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
       const int64_t l = (kp0 >> 1) + x;
-      double re = 0.0, im = 0.0;
-      if (live && l < v.L) {
-        double2 z;
-        if constexpr (TRP) {
-          using T = SplitTile<CPLX, SIDEB>;
-          z = *reinterpret_cast<const double2 *>(tile + (r - bx * T::TR) * T::PITCH +
-                                                 (l - by * T::TL) * 2);
-        } else {
-          z = X[r * v.sr + l * v.sl];
-        }
-        re = z.x;
-        im = v.conj ? -z.y : z.y;
+      if constexpr (TRP) {
+        using T = SplitTile<CPLX, SIDEB>;
+        zs[x] = *reinterpret_cast<const double2 *>(tile + (r - bx * T::TR) * T::PITCH +
+                                                   (l - by * T::TL) * 2);
+      } else {
+        zs[x] = X[(live && l < v.L) ? r * v.sr + l * v.sl : 0];
       }
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int64_t l = (kp0 >> 1) + x;
+      const bool ok = live && l < v.L;
+      const double re = ok ? zs[x].x : 0.0;
+      const double im = ok ? (v.conj ? -zs[x].y : zs[x].y) : 0.0;
       double v0, v1;
       if (!SIDEB) {
         v0 = re;
@@ -212,19 +247,21 @@ __device__ __forceinline__ void split_block(const View &v, const int *code, int 
     }
   } else {
     const double *X = reinterpret_cast<const double *>(v.base);
+    double vs[16];
 #pragma unroll
     for (int x = 0; x < 16; ++x) {
       const int64_t l = kp0 + x;
-      double val = 0.0;
-      if (live && l < v.L) {
-        if constexpr (TRP) {
-          using T = SplitTile<CPLX, SIDEB>;
-          val = tile[(r - bx * T::TR) * T::PITCH + (l - by * T::TL)];
-        } else {
-          val = X[r * v.sr + l * v.sl];
-        }
+      if constexpr (TRP) {
+        using T = SplitTile<CPLX, SIDEB>;
+        vs[x] = tile[(r - bx * T::TR) * T::PITCH + (l - by * T::TL)];
+      } else {
+        vs[x] = X[(live && l < v.L) ? r * v.sr + l * v.sl : 0];
       }
-      sg[x] = decompose(val, e);
+    }
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const int64_t l = kp0 + x;
+      sg[x] = decompose((live && l < v.L) ? vs[x] : 0.0, e);
     }
   }
 

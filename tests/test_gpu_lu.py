@@ -63,6 +63,36 @@ def test_lu_and_inverse_bit_exact(kind, s, n, nb):
     assert bits_equal(X, X_ref), mismatch_report(X, X_ref)
 
 
+@pytest.mark.parametrize("mode", ["columns", "leaf8", "leaf4", "leaf2", "auto"])
+def test_lu_panel_modes_bit_exact(mode, monkeypatch):
+    # the panel by columns (one pivot and one update launch each) and by leaves
+    # of each width held in registers: the same factors, pivots and inverse bit
+    # for bit. nb = 36 leaves a ragged last leaf in every panel (36 = 4*8 + 4),
+    # and the NaN entry makes one pivot a NaN row.
+    monkeypatch.setenv("OZAKI_LU_PANEL", mode)
+    n, nb = 150, 36
+    A = _matrix(n, 1790)
+    A[97, 40] = np.nan
+    assert oz.ozaki_set_split("t7") == 0
+    _say("lu panel mode", mode)
+    Ad, lda = dev(A)
+    ipiv = torch.zeros(n, dtype=torch.int64, device="cuda")
+    rc = oz.ozaki_zgetrf(n, Ad, lda, ipiv, nb, 5)
+    assert rc == 8, oz.ozaki_status_string(rc)       # OZAKI_ERR_SINGULAR: a NaN pivot
+    upd = lu.update_model("t7", 5)
+    LU_ref, ipiv_ref, singular = lu.zgetrf(A, nb, upd)
+    assert singular
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_ref)
+    assert bits_equal(host(Ad, n, n), LU_ref)
+    B = _matrix(n, 1791)
+    LU, ipiv, X = _gpu_lu_inv(B, nb, 5)
+    LU_ref, ipiv_ref, singular = lu.zgetrf(B, nb, upd)
+    assert not singular
+    assert np.array_equal(ipiv, ipiv_ref)
+    assert bits_equal(LU, LU_ref), mismatch_report(LU, LU_ref)
+    assert bits_equal(X, lu.zgetri(LU_ref, ipiv_ref, nb, upd))
+
+
 def test_lu_native_updates_close_to_the_model():
     n, nb = 180, 64
     A = _matrix(n, 1700)
