@@ -27,6 +27,8 @@
 // INT32 range: odd moduli have residues |r| <= 127 and K' <= 2^17 keeps every
 // sum exact; for m = 256 the accumulator wraps modulo 2^32, which keeps the
 // value modulo 256 (all the digit of that modulus reads).
+#include <type_traits>
+
 #include "ozaki2_crt.hpp"
 #include "ozaki_gemm_tile.hpp"
 
@@ -189,10 +191,12 @@ __global__ void __launch_bounds__(64 * kNW, 1) k_oz2gemm(Oz2Args G) {
     // j' = jbase + 8 (r / 4) + r % 4 (complex: r, r + 1 are Re, Im of column
     // j = j' / 2).
     const int64_t jbase = tj * BJ + wj * 32 + 4 * (lane >> 5);
-#pragma unroll
-    for (int ib = 0; ib < IB; ++ib) {
+    // one call per A' block with a compile-time block index: as a loop the
+    // compiler kept it rolled and the digit array went to scratch memory
+    auto epilogue = [&](auto ibc) {
+      constexpr int ib = decltype(ibc)::value;
       const int64_t i = ti * BI + (wi * IB + ib) * 32 + (lane & 31);
-      if (i >= G.m) continue;
+      if (i >= G.m) return;
       const int ca = G.codeA[i];
       const bool bad_i = code_bad(ca);
       const int ea = code_exp(ca) - 2 * G.beta;
@@ -243,7 +247,9 @@ __global__ void __launch_bounds__(64 * kNW, 1) k_oz2gemm(Oz2Args G) {
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-    }
+    };
+    epilogue(std::integral_constant<int, 0>{});
+    if constexpr (IB > 1) epilogue(std::integral_constant<int, 1>{});
   }
 }
 

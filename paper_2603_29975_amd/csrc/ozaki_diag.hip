@@ -48,11 +48,19 @@ __global__ void __launch_bounds__(256) k_add_diagonal(const DiagTask *tasks, con
   v16i acc = v16i{0};
   int64_t next = chunk;
   for (int64_t kb = 0; kb < nkb; ++kb) {
-    for (int p = 1; p < d; ++p) {
-      const int q = d - p;
-      const v4i b = *reinterpret_cast<const v4i *>(bp + (q - 1) * planeP + kb * kFragBytes);
-      const v4i a = *reinterpret_cast<const v4i *>(aq + (p - 1) * planeQ + kb * kFragBytes);
-      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(b, a, acc, 0, 0, 0);
+    // four slice pairs per pass, their eight fragment loads issued together
+    // (past the last pair: the last pair's fragments again, not used)
+    for (int p0 = 1; p0 < d; p0 += 4) {
+      v4i bf[4], af[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int p = p0 + x < d ? p0 + x : d - 1;
+        bf[x] = *reinterpret_cast<const v4i *>(bp + (d - p - 1) * planeP + kb * kFragBytes);
+        af[x] = *reinterpret_cast<const v4i *>(aq + (p - 1) * planeQ + kb * kFragBytes);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (p0 + x < d) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[x], af[x], acc, 0, 0, 0);
     }
     if (kb + 1 == next || kb + 1 == nkb) {
 #pragma unroll

@@ -65,6 +65,7 @@ __device__ __forceinline__ void acc_mac(Dd &acc, double a, double b) {
 }
 
 constexpr int kMaxVec = 4;
+constexpr int kBatch = 4;  // entries whose loads are issued together in the chunk loops
 
 template <bool CPLX>
 __device__ __forceinline__ double2 ld(const View &v, int64_t r, int64_t l) {
@@ -119,14 +120,22 @@ __device__ void bx_part(const ProbeTask &tk, int64_t idx) {
   const int64_t j0 = c * tk.chj, j1 = j0 + tk.chj < N ? j0 + tk.chj : N;
   Dd re[kMaxVec], im[kMaxVec];
   double u = 0.0;
-  for (int64_t j = j0; j < j1; ++j) {
-    const double2 b = ld<CPLX>(tk.vb, j, l);
-    u = add_rn(u, CPLX ? hypot(b.x, b.y) : fabs(b.x));
+  for (int64_t jb = j0; jb < j1; jb += kBatch) {
+    double2 bq[kBatch];  // the batch's loads first (past j1: the last entry again)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double s = sign_of(tk.seed, v, N, j);
-      acc_add(re[v], mul_rn(s, b.x));
-      if (CPLX) acc_add(im[v], mul_rn(s, b.y));
+    for (int q = 0; q < kBatch; ++q) bq[q] = ld<CPLX>(tk.vb, jb + q < j1 ? jb + q : j1 - 1, l);
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int64_t j = jb + q;
+      if (j >= j1) break;
+      const double2 b = bq[q];
+      u = add_rn(u, CPLX ? hypot(b.x, b.y) : fabs(b.x));
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double s = sign_of(tk.seed, v, N, j);
+        acc_add(re[v], mul_rn(s, b.x));
+        if (CPLX) acc_add(im[v], mul_rn(s, b.y));
+      }
     }
   }
   put_rec<NV>(tk.p1 + (c * K + l) * kRec, re, im, u);
@@ -140,6 +149,7 @@ __device__ void bx_sum(const ProbeTask &tk, int64_t l) {
   if (l >= K) return;
   Dd re[kMaxVec], im[kMaxVec];
   double u = 0.0;
+#pragma unroll 4
   for (int64_t c = 0; c < tk.ncj; ++c) add_rec<NV>(tk.p1 + (c * K + l) * kRec, re, im, u);
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -164,46 +174,78 @@ __device__ void rows_part(const ProbeTask &tk, int64_t idx) {
   double u = 0.0;
   if (c < tk.ncl) {
     const int64_t l0 = c * tk.chl, l1 = l0 + tk.chl < K ? l0 + tk.chl : K;
-    for (int64_t l = l0; l < l1; ++l) {
-      const double2 a = ld<CPLX>(tk.va, i, l);
-      u = add_rn(u, mul_rn(CPLX ? hypot(a.x, a.y) : fabs(a.x), tk.ub[l]));
-  #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double *o = tk.w + (l * kMaxVec + v) * 4;
-        // (ar + i ai)(wr + i wi) with w = hi + lo in both parts
-        acc_mac(xr[v], a.x, o[0]);
-        acc_mac(xr[v], a.x, o[1]);
-        if (CPLX) {
-          acc_mac(xr[v], -a.y, o[2]);
-          acc_mac(xr[v], -a.y, o[3]);
-          acc_mac(xi[v], a.x, o[2]);
-          acc_mac(xi[v], a.x, o[3]);
-          acc_mac(xi[v], a.y, o[0]);
-          acc_mac(xi[v], a.y, o[1]);
+    for (int64_t lb = l0; lb < l1; lb += kBatch) {
+      // the batch's loads first (past l1: the last entry again)
+      double2 aq[kBatch];
+      double ubq[kBatch], oq[kBatch][NV][4];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int64_t lq = lb + q < l1 ? lb + q : l1 - 1;
+        aq[q] = ld<CPLX>(tk.va, i, lq);
+        ubq[q] = tk.ub[lq];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) oq[q][v][e] = tk.w[(lq * kMaxVec + v) * 4 + e];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (lb + q >= l1) break;
+        const double2 a = aq[q];
+        u = add_rn(u, mul_rn(CPLX ? hypot(a.x, a.y) : fabs(a.x), ubq[q]));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double *o = oq[q][v];
+          // (ar + i ai)(wr + i wi) with w = hi + lo in both parts
+          acc_mac(xr[v], a.x, o[0]);
+          acc_mac(xr[v], a.x, o[1]);
+          if (CPLX) {
+            acc_mac(xr[v], -a.y, o[2]);
+            acc_mac(xr[v], -a.y, o[3]);
+            acc_mac(xi[v], a.x, o[2]);
+            acc_mac(xi[v], a.x, o[3]);
+            acc_mac(xi[v], a.y, o[0]);
+            acc_mac(xi[v], a.y, o[1]);
+          }
         }
       }
     }
   } else {
     const int64_t j0 = (c - tk.ncl) * tk.chj, j1 = j0 + tk.chj < N ? j0 + tk.chj : N;
-    for (int64_t j = j0; j < j1; ++j) {
-      double cr, ci = 0.0;
-      if (CPLX) {
-        const double2 cz = reinterpret_cast<const double2 *>(tk.C)[i + j * tk.ldc];
-        cr = cz.x;
-        ci = cz.y;
-      } else {
-        cr = reinterpret_cast<const double *>(tk.C)[i + j * tk.ldc];
+    const int ea = tk.codeA != nullptr ? code_exp(tk.codeA[i]) : 0;
+    for (int64_t jb = j0; jb < j1; jb += kBatch) {
+      // the batch's loads first (past j1: the last entry again)
+      double crq[kBatch], ciq[kBatch];
+      int cbq[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int64_t jq = jb + q < j1 ? jb + q : j1 - 1;
+        if (CPLX) {
+          const double2 cz = reinterpret_cast<const double2 *>(tk.C)[i + jq * tk.ldc];
+          crq[q] = cz.x;
+          ciq[q] = cz.y;
+        } else {
+          crq[q] = reinterpret_cast<const double *>(tk.C)[i + jq * tk.ldc];
+          ciq[q] = 0.0;
+        }
+        cbq[q] = tk.codeA != nullptr ? tk.codeB[jq] : 0;
       }
-      if (tk.codeA != nullptr) {
-        const int sc = code_exp(tk.codeA[i]) + code_exp(tk.codeB[j]);
-        cr = ldexp(cr, sc);
-        ci = ldexp(ci, sc);
-      }
-  #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double s = sign_of(tk.seed, v, N, j);
-        acc_add(xr[v], mul_rn(s, cr));
-        if (CPLX) acc_add(xi[v], mul_rn(s, ci));
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int64_t j = jb + q;
+        if (j >= j1) break;
+        double cr = crq[q], ci = ciq[q];
+        if (tk.codeA != nullptr) {
+          const int sc = ea + code_exp(cbq[q]);
+          cr = ldexp(cr, sc);
+          ci = ldexp(ci, sc);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double s = sign_of(tk.seed, v, N, j);
+          acc_add(xr[v], mul_rn(s, cr));
+          if (CPLX) acc_add(xi[v], mul_rn(s, ci));
+        }
       }
     }
   }
@@ -217,7 +259,9 @@ __device__ void rows_sum(const ProbeTask &tk, int64_t i) {
   if (i >= M) return;
   Dd zr[kMaxVec], zi[kMaxVec], yr[kMaxVec], yi[kMaxVec];
   double u = 0.0, unused = 0.0;
+#pragma unroll 4
   for (int64_t c = 0; c < tk.ncl; ++c) add_rec<NV>(tk.p2 + (c * M + i) * kRec, zr, zi, u);
+#pragma unroll 4
   for (int64_t c = tk.ncl; c < tk.ncl + tk.ncj; ++c)
     add_rec<NV>(tk.p2 + (c * M + i) * kRec, yr, yi, unused);
   double ss = 0.0;
