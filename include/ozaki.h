@@ -204,6 +204,11 @@ size_t ozaki2_workspace_bytes(char kind, int64_t m, int64_t n, int64_t k, int mo
  *   to the other columns, U12 = L11^-1 A12 (forward substitution), then
  *   A22 -= L21 U12. Returns OZAKI_ERR_SINGULAR (factors complete) if a pivot
  *   is exactly zero or NaN. Synchronises with the stream before returning.
+ *   The panel runs in leaves of up to 8 columns held in registers by one
+ *   workgroup while at most 8192 rows lie below the leaf, else column by
+ *   column; OZAKI_LU_PANEL=columns, leaf8, leaf4 or leaf2 in the environment
+ *   (read at every call) forces a form. Every form gives the same factors and
+ *   pivots bit for bit.
  * ozaki_zgetri: X (device, ldx >= n, not overlapping LU) = A^-1 from the
  *   factors: X = P I (an ipiv entry outside [c, n) counts as no exchange);
  *   block rows of nb top down X_i = L_ii^-1 X_i, X_below -=

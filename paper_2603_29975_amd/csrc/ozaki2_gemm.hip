@@ -268,10 +268,12 @@ template <int N>
 hipError_t launch_n(const Oz2Args &a, int num_cu, hipStream_t st) {
   // two A' blocks per wave while the digits of 2 x 16 entries fit the
   // registers (N <= 16: 4 words per entry), else one. Measured at 2048^3
-  // complex, 13 moduli: a five-stage ring (160 KiB) and an eight-stage ring of
-  // two-block stages were no faster (0.765 and 0.975 ms against 0.762 ms),
-  // one A' block per wave slower (0.892 ms).
-  constexpr int IB = N <= 16 ? 2 : 1;
+  // complex (GEMM per launch): 13 moduli 0.687 ms with two blocks, 0.824 with
+  // one; 15 moduli 0.762 against 0.958; at 14 moduli the compiler spills 79
+  // registers in the main loop with two blocks (1.010 ms) and one block is
+  // faster (0.900 ms). A five-stage ring (160 KiB) and an eight-stage ring of
+  // two-block stages were no faster at 13 moduli.
+  constexpr int IB = (N <= 16 && N != 14) ? 2 : 1;
   return launch_v<N, IB, kRing, kStep>(a, num_cu, st);
 }
 

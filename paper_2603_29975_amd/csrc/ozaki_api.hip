@@ -360,6 +360,7 @@ GemmArgs gemm_args(const Plan &p, char *ws, double ar, double ai, double br, dou
   a.flush_ws = reinterpret_cast<int64_t *>(ws + p.off_flush);
   a.kb_chunk = p.kb_chunk;
   a.chunked = p.nkb > p.kb_chunk ? 1 : 0;
+  a.split = (a.chunked && p.nkb <= kb_split_for(p.S, p.b8)) ? 1 : 0;
   a.max_groups = g.grid_limit;
   return a;
 }

@@ -25,9 +25,11 @@
 // natural operand reuse: each fragment feeds (S+1)/2 MFMAs on average.
 //
 // INT32 range: a diagonal of S pairs over 32*kb contraction entries is bounded
-// by S * 32 * kb * 127^2; the contraction is cut into chunks that keep it
-// below 2^31 and each chunk is carried exactly into int64 workgroup-private
-// memory. The FP64 epilogue converts every S_t exactly (|S_t| < 2^53) and adds
+// by S * 32 * kb * 127^2. Past that bound a single product with one A' block
+// per wave splits each diagonal's pairs over two INT32 sets (p below or from
+// ceil(S/2)), which doubles the reach; beyond that, or with two A' blocks per
+// wave, the contraction is cut into chunks that keep each sum below 2^31 and
+// each chunk is carried exactly into int64 workgroup-private memory. The FP64 epilogue converts every S_t exactly (|S_t| < 2^53) and adds
 // them largest weight first, one rounding per addition, then scales by
 // 2^(e_i + f_j) and applies alpha/beta without fused multiply-adds.
 #include "ozaki_gemm_tile.hpp"
@@ -59,9 +61,12 @@ using tile::chunk_blocks;
 using tile::wait_vmcnt;
 
 template <int S, int WJ, int WI, int IB, int NBUF, bool RAW, bool CHUNKED, bool GROUPED,
-          bool EARLY>
+          bool EARLY, bool SPLIT = false>
 __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(GemmArgs G) {
   using C_ = Cfg<S, WJ, WI, IB, NBUF>;
+  static_assert(!(SPLIT && (CHUNKED || RAW)), "split accumulation replaces the carry");
+  constexpr int PM = tile::split_pm(S);
+  constexpr int XN = SPLIT ? tile::split_extra(S) : 0;
   __shared__ __attribute__((aligned(16))) int8_t lds[C_::LDS];
 
   const int lane = threadIdx.x & 63;
@@ -105,10 +110,14 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
     };
 
     v16i acc[IB][S];
+    v16i accx[IB][XN > 0 ? XN : 1];
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib)
+    for (int ib = 0; ib < IB; ++ib) {
 #pragma unroll
       for (int t = 0; t < S; ++t) acc[ib][t] = v16i{0};
+#pragma unroll
+      for (int t = 0; t < XN; ++t) accx[ib][t] = v16i{0};
+    }
 
     // Exact int64 carry of the INT32 accumulators (chunked contraction only).
     int64_t *ws = G.flush_ws + ((int64_t)blockIdx.x * C_::NW + wave) * (int64_t)IB * S * 1024;
@@ -175,9 +184,14 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
 #pragma unroll
         for (int ib = 0; ib < IB; ++ib) {
 #pragma unroll
-          for (int q = 0; q < S - p; ++q)
-            acc[ib][p + q] =
-                __builtin_amdgcn_mfma_i32_32x32x32_i8(pf[q], qf[p][ib], acc[ib][p + q], 0, 0, 0);
+          for (int q = 0; q < S - p; ++q) {
+            if (XN > 0 && p >= PM)  // the second set of diagonal p + q
+              accx[ib][p + q - PM] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                  pf[q], qf[p][ib], accx[ib][p + q - PM], 0, 0, 0);
+            else
+              acc[ib][p + q] =
+                  __builtin_amdgcn_mfma_i32_32x32x32_i8(pf[q], qf[p][ib], acc[ib][p + q], 0, 0, 0);
+          }
         }
       }
       if constexpr (chunked) {
@@ -198,9 +212,9 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
     // ------------------------------------------------------------ epilogue
 #pragma unroll
     for (int ib = 0; ib < IB; ++ib)
-      tile::store_block<S, CHUNKED, RAW>(a, acc[ib], ws + ib * S * 1024, lane,
-                                         ti * C_::BI + (wi * IB + ib) * 32 + (lane & 31),
-                                         tj * C_::BJ + wj * 32 + 4 * (lane >> 5));
+      tile::store_block<S, CHUNKED, RAW, XN>(a, acc[ib], ws + ib * S * 1024, lane,
+                                             ti * C_::BI + (wi * IB + ib) * 32 + (lane & 31),
+                                             tj * C_::BJ + wj * 32 + 4 * (lane >> 5), accx[ib]);
   }
 }
 
@@ -233,7 +247,20 @@ hipError_t launch_cfg(const GemmArgs &a, int num_cu, hipStream_t st) {
       return hipErrorInvalidValue;
     }
   } else {
-    if (a.chunked)
+    // a contraction each of whose diagonals fits two INT32 sets takes the
+    // split accumulation where its extra sets fit the registers (one A' block
+    // per wave, S <= 7; two blocks' extra sets, or S >= 8, spill)
+    bool split = false;
+    if constexpr (IB == 1 && S >= 2 && S <= 7) {
+      if (a.chunked && a.split) {
+        hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, false, EARLY, true>), g, b,
+                           0, st, a);
+        split = true;
+      }
+    }
+    if (split)
+      ;
+    else if (a.chunked)
       hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, true, false, EARLY>), g, b, 0, st, a);
     else
       hipLaunchKernelGGL((k_ozgemm<S, WJ, WI, IB, NBUF, false, false, false, EARLY>), g, b, 0, st, a);
@@ -325,6 +352,7 @@ constexpr int waves_of() {
 }  // namespace
 
 int64_t kb_chunk_for(int S, bool b8) { return chunk_blocks(S, b8 ? 128 : 127); }
+int64_t kb_split_for(int S, bool b8) { return chunk_blocks(tile::split_pm(S), b8 ? 128 : 127); }
 
 int gemm_num_configs() { return 4 * kNumCfg; }
 

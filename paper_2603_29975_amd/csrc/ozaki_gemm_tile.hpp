@@ -74,17 +74,25 @@ __device__ __forceinline__ void carry_block(v16i (&acc)[S], int64_t *ws, int lan
   }
 }
 
+// Split accumulation: diagonal t (t + 1 slice pairs) keeps the pairs with
+// p < split_pm(S) in one INT32 set and the others (at most as many) in a
+// second, so a contraction of up to chunk_blocks(split_pm(S)) blocks needs no
+// int64 carry; the two sets add exactly in int64 in the epilogue.
+__host__ __device__ constexpr int split_pm(int S) { return (S + 1) / 2; }
+__host__ __device__ constexpr int split_extra(int S) { return S - split_pm(S); }
+
 // Recombination and store of one 32 x 32 block: row i of the output, lane
 // register r at column side j' = jbase + 8 (r / 4) + r % 4. Diagonal t + 2 of
-// the block is acc[t] (or, for a chunked contraction, the int64 total in the
-// carry space `ws`). acc = RN(acc + S_t 2^(woff - wbits t)) for t = 2..S+1
-// (2^-7t for trunc-7 slices, 2^(4-8t) for 8-bit balanced ones), then
-// ldexp(acc, e_i + f_j) and alpha/beta without fused multiply-adds; rows or
-// columns flagged non-finite give NaN. RAW writes the exact diagonals instead.
-template <int S, bool CHUNKED, bool RAW>
+// the block is acc[t] (plus accx[t - split_pm(S)] for t >= split_pm(S) when XN
+// > 0; or, for a chunked contraction, the int64 total in the carry space
+// `ws`). acc = RN(acc + S_t 2^(woff - wbits t)) for t = 2..S+1 (2^-7t for
+// trunc-7 slices, 2^(4-8t) for 8-bit balanced ones), then ldexp(acc, e_i +
+// f_j) and alpha/beta without fused multiply-adds; rows or columns flagged
+// non-finite give NaN. RAW writes the exact diagonals instead.
+template <int S, bool CHUNKED, bool RAW, int XN = 0>
 __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&acc)[S],
                                             const int64_t *ws, int lane, int64_t i,
-                                            int64_t jbase) {
+                                            int64_t jbase, const v16i *accx = nullptr) {
   const bool row_ok = i < a.m;
   const int codeA = row_ok ? a.codeA[i] : 0;
 
@@ -93,6 +101,9 @@ __device__ __forceinline__ void store_block(const GemmProblem &a, const v16i (&a
   auto total = [&](int t, int r) -> int64_t {
     if constexpr (CHUNKED)
       return __hip_atomic_load(q + (t * 16 + r) * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (XN > 0) {
+      if (t >= S - XN) return (int64_t)acc[t][r] + (int64_t)accx[t - (S - XN)][r];
+    }
     return (int64_t)acc[t][r];
   };
 

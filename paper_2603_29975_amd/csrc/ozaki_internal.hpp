@@ -87,6 +87,7 @@ struct GemmArgs {
   int64_t *flush_ws;  // int64 per-workgroup carry space (chunked K only)
   int64_t kb_chunk;   // contraction blocks per exact INT32 chunk
   int chunked;        // some problem has nkb > kb_chunk
+  int split;          // single product: nkb fits two INT32 sets per diagonal (see split_pm)
   int order;          // tile order (set from the tuning id at launch)
   int64_t max_groups; // cap on the persistent grid (0: no cap beyond the CU count)
 };
@@ -99,6 +100,10 @@ hipError_t launch_ozgemm_grouped(int S, int cfg, const GemmArgs &a, int num_cu, 
 // Contraction blocks (of 32) that one INT32 accumulation may cover for S
 // slices: S * 32 * kb * 127^2 < 2^31 (8-bit slices: 128^2).
 int64_t kb_chunk_for(int S, bool b8 = false);
+// Contraction blocks up to which a chunked single product instead splits each
+// diagonal's slice pairs over two INT32 sets (configurations with one A'
+// block per wave), so that it needs no int64 carry.
+int64_t kb_split_for(int S, bool b8 = false);
 // Tuning ids of the fused GEMM (0 .. gemm_num_configs() - 1): 2 * tile
 // configuration + tile order.
 int gemm_num_configs();

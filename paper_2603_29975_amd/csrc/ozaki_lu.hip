@@ -153,11 +153,47 @@ __global__ void __launch_bounds__(256) k_panel_scale(double2 *A, int64_t lda, in
   st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
 }
 
+// One step of a wave's pivot reduction with a DPP lane pattern (VALU moves, no
+// LDS round trip): each lane compares with the lane CTRL names.
+template <int CTRL>
+__device__ __forceinline__ void best_dpp(double &best, int64_t &bi) {
+  const int64_t vb = __double_as_longlong(best);
+  const int vlo = (int)vb, vhi = (int)(vb >> 32), ilo = (int)bi, ihi = (int)(bi >> 32);
+  const int ovlo = __builtin_amdgcn_update_dpp(vlo, vlo, CTRL, 0xF, 0xF, false);
+  const int ovhi = __builtin_amdgcn_update_dpp(vhi, vhi, CTRL, 0xF, 0xF, false);
+  const int oilo = __builtin_amdgcn_update_dpp(ilo, ilo, CTRL, 0xF, 0xF, false);
+  const int oihi = __builtin_amdgcn_update_dpp(ihi, ihi, CTRL, 0xF, 0xF, false);
+  const double ov = __longlong_as_double((int64_t)(((uint64_t)(uint32_t)ovhi << 32) | (uint32_t)ovlo));
+  const int64_t oi = (int64_t)(((uint64_t)(uint32_t)oihi << 32) | (uint32_t)oilo);
+  const bool take = beats(ov, oi, best, bi);
+  best = take ? ov : best;
+  bi = take ? oi : bi;
+}
+
+// The wave's best (value, row) in every lane: within each 16-lane row by DPP
+// (quad exchanges 1 and 2, then half-row and row mirrors), across rows by two
+// shuffles. The order of comparisons does not matter: `beats` is a strict
+// total order on (value, row) pairs.
+__device__ __forceinline__ void wave_best(double &best, int64_t &bi) {
+  best_dpp<0xB1>(best, bi);   // quad_perm [1, 0, 3, 2]
+  best_dpp<0x4E>(best, bi);   // quad_perm [2, 3, 0, 1]
+  best_dpp<0x141>(best, bi);  // row_half_mirror
+  best_dpp<0x140>(best, bi);  // row_mirror
+#pragma unroll
+  for (int o = 16; o < 64; o <<= 1) {
+    const double ov = __shfl_xor(best, o);
+    const int64_t oi = __shfl_xor(bi, o);
+    const bool take = beats(ov, oi, best, bi);
+    best = take ? ov : best;
+    bi = take ? oi : bi;
+  }
+}
+
 // A leaf of the panel: the columns [c0, c1) (at most L) over the rows [c0, n),
 // factored by one workgroup with every entry in registers (thread t holds rows
 // c0 + t + 512 j, j < RPT, of each leaf column), so the L dependent steps cost
 // one barrier each instead of two kernel launches. Step c:
-//   pivot: each wave reduces its rows with shuffles; the lane holding the
+//   pivot: each wave reduces its rows (DPP, two shuffles); the lane holding the
 //     wave's best row copies that row of the leaf to LDS (and lane c - c0,
 //     which holds row c, copies row c); after the barrier every thread reduces
 //     the 8 wave results itself and reads the pivot row from its wave's slot;
@@ -209,14 +245,7 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
       best = take ? cabs1(x[j][cc]) : best;
       bi = take ? i : bi;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
-      const int64_t oi = __shfl_xor(bi, o);
-      const bool take = beats(ov, oi, best, bi);
-      best = take ? ov : best;
-      bi = take ? oi : bi;
-    }
+    wave_best(best, bi);
     if (bi < n && ((bi - c0) & (NT - 1)) == t) {
       const int jb = (int)((bi - c0) / NT);
 #pragma unroll
@@ -530,71 +559,110 @@ __global__ void __launch_bounds__(256) k_apply_pairs(double2 *A, int64_t lda, in
     if (d[j] >= 0) col[d[j]] = v[j];
 }
 
-// Wait for this wave's LDS accesses, then the workgroup barrier alone: no
-// wait for global loads, so prefetches stay in flight across it.
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+// Lane l's value of v, read by every lane (l uniform): two v_readlane.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
-#pragma clang diagnostic pop
 
 // X <- T^-1 X for the nb x nb triangle T (at T, leading dimension ldt) on
-// ncols columns of X, column-oriented: one workgroup per column, thread r
-// holds x_r. Unit lower (forward): for k = 0, 1, ..., x_k is final and every
-// x_r with r > k takes x_r -= t_rk x_k. Non-unit upper (backward): for
-// k = nb-1 down to 0, x_k = x_k / t_kk is final and every x_r with r < k takes
-// x_r -= t_rk x_k. Each x_r thus subtracts its terms in the order of k (forward:
-// increasing, backward: decreasing). One barrier per step; the final x_k goes
-// through LDS slot k. Thread r loads its t_rk kPre steps ahead into a ring of
-// registers, so the L2 latency of T is off the chain of steps.
-template <bool UPPER>
-__global__ void __launch_bounds__(1024) k_trsm(const double2 *T, int64_t ldt, int nb, double2 *X,
-                                               int64_t ldx) {
-  constexpr int kPre = 8;
-  __shared__ double2 xs[1024];
-  const int r = threadIdx.x;
-  // Every thread issues exactly one load per step (threads past nb and steps
-  // that take no term read an entry inside the triangle's nb x nb block), so
-  // the outstanding-load count is the same on every path and the compiler
-  // waits for the one load each step needs rather than for all of them.
-  const int rr = r < nb ? r : nb - 1;
-  const double2 *trow = T + rr;  // t_rk at trow[k * ldt]
-  double2 *x = X + (int64_t)blockIdx.x * ldx;
-  Z xr = ld(x + rr);
-  if (r >= nb) xr = Z{0.0, 0.0};
+// ncols columns of X, column-oriented. Unit lower (forward): for k = 0, 1,
+// ..., x_k is final and every x_r with r > k takes x_r -= t_rk x_k. Non-unit
+// upper (backward): for k = nb-1 down to 0, x_k = x_k / t_kk is final and
+// every x_r with r < k takes x_r -= t_rk x_k. Each x_r thus subtracts its
+// terms in the order of k (forward: increasing, backward: decreasing). One
+// wave per CW columns of X: lane l holds x_r of each of them for the rows
+// r = l + 64 j (j < R, nb <= 64 R), so a step needs no barrier: the final x_k
+// comes from its lane by v_readlane and every lane updates its own rows. Each
+// t_rk is loaded once per wave and used for all CW columns. Each lane loads
+// its t_rk kPre steps ahead into a ring of registers (one load per row slot
+// and step; rows past nb read row nb - 1, steps past the last read the last
+// column), so the L2 latency of T is off the chain of steps. One column per
+// wave measured fastest: with four, the waves were a quarter as many and each
+// step four times longer (2048 KKR inverse: upper solves 53 -> 87 us).
+constexpr int kTrsmCols = 1;
+
+template <bool UPPER, int R>
+__global__ void __launch_bounds__(256) k_trsm(const double2 *T, int64_t ldt, int nb, double2 *X,
+                                              int64_t ldx, int64_t ncols) {
+  constexpr int CW = kTrsmCols;
+  constexpr int kPre = R <= 2 ? 8 : (R >= 16 ? 1 : 16 / R);
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * CW;
+  if (c0 >= ncols) return;  // a whole wave
+  Z xr[R][CW], dg[R];
+  int rr[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int r = lane + 64 * j;
+    rr[j] = r < nb ? r : nb - 1;
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+      xr[j][c] = (r < nb && c0 + c < ncols) ? ld(X + (c0 + c) * ldx + r) : Z{0.0, 0.0};
+    dg[j] = UPPER ? ld(T + rr[j] + (int64_t)rr[j] * ldt) : Z{1.0, 0.0};
+  }
   const int steps = UPPER ? nb : nb - 1;
   auto col = [&](int s) { return UPPER ? nb - 1 - s : s; };
   if (steps > 0) {
-    const Z diag = UPPER ? ld(trow + (int64_t)rr * ldt) : Z{1.0, 0.0};
-    Z ring[kPre];
+    Z ring[kPre][R];
 #pragma unroll
-    for (int j = 0; j < kPre; ++j) ring[j] = ld(trow + (int64_t)col(j < steps ? j : steps - 1) * ldt);
-    // steps past the last one (up to a multiple of kPre) take no term and
-    // write nothing; they keep every group of kPre steps alike
+    for (int p = 0; p < kPre; ++p) {
+      const int64_t kk = col(p < steps ? p : steps - 1);
+#pragma unroll
+      for (int j = 0; j < R; ++j) ring[p][j] = ld(T + rr[j] + kk * ldt);
+      // slot order kept: the loop's waits count on slot 0 being the oldest
+      __builtin_amdgcn_sched_barrier(0);
+    }
     for (int s0 = 0; s0 < steps; s0 += kPre) {
 #pragma unroll
-      for (int j = 0; j < kPre; ++j) {
-        const int s = s0 + j;
-        const int k = col(s);
-        const bool live = s < steps;
-        if (live && r == k) {
-          if constexpr (UPPER) xr = zdiv(xr, diag);
-          xs[k] = make_double2(xr.re, xr.im);
+      for (int p = 0; p < kPre; ++p) {
+        const int s = s0 + p;
+        if (s < steps) {
+          const int k = col(s);
+          const int kl = k & 63, ks = k >> 6;
+          if constexpr (UPPER) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+              if (j == ks && lane == kl)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) xr[j][c] = zdiv(xr[j][c], dg[j]);
+          }
+          Z u[CW];
+#pragma unroll
+          for (int c = 0; c < CW; ++c) {
+            Z cur = xr[0][c];
+#pragma unroll
+            for (int j = 1; j < R; ++j)
+              if (j == ks) cur = xr[j][c];
+            u[c] = Z{readlane_d(cur.re, kl), readlane_d(cur.im, kl)};
+          }
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const int r = lane + 64 * j;
+            if (r < nb && (UPPER ? r < k : r > k))
+#pragma unroll
+              for (int c = 0; c < CW; ++c) xr[j][c] = zsub(xr[j][c], zmul(ring[p][j], u[c]));
+          }
         }
-        lds_barrier();
-        if (live && r < nb && (UPPER ? r < k : r > k)) {
-          const double2 v = xs[k];
-          xr = zsub(xr, zmul(ring[j], Z{v.x, v.y}));
-        }
-        // the slot's next load goes out once its value is used, straight
-        // into the same registers
+        // the slot's next load goes out once its value is used; the scheduling
+        // barrier keeps the compiler from hoisting it above the use, where the
+        // in-order load counter would make this step wait for every newer
+        // prefetch
+        __builtin_amdgcn_sched_barrier(0);
         const int sn = s + kPre < steps ? s + kPre : steps - 1;
-        ring[j] = ld(trow + (int64_t)col(sn) * ldt);
+        const int64_t kk = col(sn);
+#pragma unroll
+        for (int j = 0; j < R; ++j) ring[p][j] = ld(T + rr[j] + kk * ldt);
       }
     }
   }
-  if (r < nb) st(x + r, xr);
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (lane + 64 * j < nb)
+#pragma unroll
+      for (int c = 0; c < CW; ++c)
+        if (c0 + c < ncols) st(X + (c0 + c) * ldx + lane + 64 * j, xr[j][c]);
 }
 
 // X = identity (n x n, leading dimension ldx).
@@ -708,12 +776,27 @@ hipError_t launch_apply_pairs(double2 *A, int64_t lda, int64_t w, const int64_t 
 hipError_t launch_trsm(bool upper, const double2 *T, int64_t ldt, int64_t nb, double2 *X,
                        int64_t ldx, int64_t ncols, hipStream_t st) {
   if (ncols <= 0 || nb <= 0) return hipSuccess;
-  if (nb > kLuMaxBlock || ncols > 0x7fffffffll) return hipErrorInvalidValue;
-  const dim3 block((unsigned)((nb + 63) / 64 * 64));
-  if (upper)
-    hipLaunchKernelGGL(k_trsm<true>, dim3((unsigned)ncols), block, 0, st, T, ldt, (int)nb, X, ldx);
-  else
-    hipLaunchKernelGGL(k_trsm<false>, dim3((unsigned)ncols), block, 0, st, T, ldt, (int)nb, X, ldx);
+  const int64_t waves = (ncols + kTrsmCols - 1) / kTrsmCols;
+  if (nb > kLuMaxBlock || (waves + 3) / 4 > 0x7fffffffll) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((waves + 3) / 4)), b(256);
+  const int n = (int)nb;
+#define OZ_TRSM(RR)                                                                            \
+  if (upper)                                                                                   \
+    hipLaunchKernelGGL((k_trsm<true, RR>), g, b, 0, st, T, ldt, n, X, ldx, ncols);            \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_trsm<false, RR>), g, b, 0, st, T, ldt, n, X, ldx, ncols);
+  if (nb <= 64) {
+    OZ_TRSM(1)
+  } else if (nb <= 128) {
+    OZ_TRSM(2)
+  } else if (nb <= 256) {
+    OZ_TRSM(4)
+  } else if (nb <= 512) {
+    OZ_TRSM(8)
+  } else {
+    OZ_TRSM(16)
+  }
+#undef OZ_TRSM
   return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ __device__ __forceinline__ int feat_bin(int c, int rc, int nbins) {
 
 // One block per task and row group: 256 threads walk the rows of the group
 // (64 rows with 4 threads each when rows are unit-stride, else 4 rows with a
-// wave each) over the whole contraction, into an LDS histogram.
+// wave each) over the whole contraction, into an LDS histogram; the loads of
+// four entries are issued together.
 template <bool CPLX>
 __device__ void feat_block(const FeatTask &t, int64_t rb) {
   __shared__ int hist[32];
@@ -59,20 +60,31 @@ __device__ void feat_block(const FeatTask &t, int64_t rb) {
   if (tid < 32) hist[tid] = 0;
   __syncthreads();
   const View &v = t.v;
+  int64_t r, l, step, off0, stride;
   if (t.rows_fast) {
-    const int64_t r = rb * 64 + (tid & 63);
-    if (r < v.R) {
-      const int rc = t.code[r];
-      for (int64_t l = tid >> 6; l < v.L; l += 4)
-        atomicAdd(&hist[feat_bin(elem_code2<CPLX>(v.base, r + l * v.sl), rc, t.nbins)], 1);
-    }
+    r = rb * 64 + (tid & 63);
+    l = tid >> 6;
+    step = 4;
+    off0 = r;
+    stride = v.sl;
   } else {
-    const int64_t r = rb * 4 + (tid >> 6);
-    if (r < v.R) {
-      const int rc = t.code[r];
-      for (int64_t l = tid & 63; l < v.L; l += 64)
-        atomicAdd(&hist[feat_bin(elem_code2<CPLX>(v.base, r * v.sr + l), rc, t.nbins)], 1);
+    r = rb * 4 + (tid >> 6);
+    l = tid & 63;
+    step = 64;
+    off0 = r * v.sr;
+    stride = 1;
+  }
+  if (r < v.R) {
+    const int rc = t.code[r];
+    for (; l + 3 * step < v.L; l += 4 * step) {
+      int cq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cq[q] = elem_code2<CPLX>(v.base, off0 + (l + q * step) * stride);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) atomicAdd(&hist[feat_bin(cq[q], rc, t.nbins)], 1);
     }
+    for (; l < v.L; l += step)
+      atomicAdd(&hist[feat_bin(elem_code2<CPLX>(v.base, off0 + l * stride), rc, t.nbins)], 1);
   }
   __syncthreads();
   if (tid < t.nbins && hist[tid] != 0) atomicAdd(t.hist + tid, hist[tid]);

@@ -81,6 +81,29 @@ def test_chunked_carry_many_tiles_every_id(split, kind, m, n, k, s):
             assert bits_equal(got, ref), f"id {tid} limit {limit}\n" + mismatch_report(got, ref)
 
 
+# Contractions beyond the reach of the split accumulation (each diagonal's
+# pairs over two INT32 sets: 1040 blocks for trunc-7 s = 7, 1365 for 8-bit
+# s = 6, 1386 for trunc-7 s = 5), so every configuration takes the int64 carry;
+# the shapes above are within it, where the configurations with one A' block
+# per wave split instead of carrying.
+@pytest.mark.parametrize("split,kind,m,n,k,s", [("t7", "z", 48, 40, 17000, 7),
+                                                ("b8", "z", 40, 33, 22000, 6),
+                                                ("t7", "d", 37, 29, 45000, 5)])
+def test_chunked_beyond_split_reach_every_id(split, kind, m, n, k, s):
+    assert oz.ozaki_set_split(split) == 0
+    A, B = scaled_gaussian(m, n, k, seed=830 + s, rmax=20, complex_=kind == "z")
+    rng = np.random.default_rng(831)
+    dt = np.complex128 if kind == "z" else np.float64
+    C0 = rng.standard_normal((m, n)).astype(dt)
+    alpha, beta = (0.5 + 0.25j, 0.5 - 1.0j) if kind == "z" else (-0.75, 2.0)
+    ref = _model(split)("N", "N", A, B, s, alpha, beta, C0)
+    for tid in range(oz.ozaki_tune_configs()):
+        assert oz.ozaki_tune_set(kind, m, n, k, s, tid) == 0
+        _say(f"chunked beyond split {split} {kind} {(m, n, k)} s={s} tuning id {tid}")
+        got = _gemm(kind, A, B, s, alpha, beta, C0)
+        assert bits_equal(got, ref), f"id {tid}\n" + mismatch_report(got, ref)
+
+
 def test_grid_limit_rejects_negative():
     assert oz.ozaki_set_grid_limit(-1) == -1
     assert oz.ozaki_set_grid_limit(0) == 0
