@@ -154,45 +154,76 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
         issue(kb + D, nb);
       }
       const int8_t *L = lds + buf * C_::STAGE;
-      // All fragment reads of the block are issued up front, A' of slice 1
-      // first; a wave's LDS reads return in order, so each MFMA waits only for
-      // the reads it needs and the later ones arrive under the earlier MFMAs.
-      v4i qf[S][IB];
+      // One MFMA of slice pair (p, q) into the set of diagonal p + q.
+      auto mfma = [&](int p, int q, int ib, const v4i &pq, const v4i &qp) {
+        if (XN > 0 && p >= PM)  // the second set of diagonal p + q
+          accx[ib][p + q - PM] =
+              __builtin_amdgcn_mfma_i32_32x32x32_i8(pq, qp, accx[ib][p + q - PM], 0, 0, 0);
+        else
+          acc[ib][p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(pq, qp, acc[ib][p + q], 0, 0, 0);
+      };
+      auto read_q = [&](int p, int ib) {
+        return *reinterpret_cast<const v4i *>(L + (C_::NFP + p * C_::NQB + wi * IB + ib) * kFragBytes +
+                                              lane * 16);
+      };
+      if constexpr (IB >= 2 && !EARLY) {
+        // Two A' blocks per wave: the fragments of every slice do not fit the
+        // registers next to the 2 S accumulator sets, and left to itself the
+        // compiler read each A' fragment into one register set just before
+        // its MFMAs, waiting out every LDS latency. Here the A' reads of slice
+        // p + 1 go out before the MFMAs of slice p (two register sets), the
+        // order pinned by scheduling barriers.
+        v4i pf[S], qa[IB], qb[IB];
 #pragma unroll
-      for (int ib = 0; ib < IB; ++ib)
-        qf[0][ib] = *reinterpret_cast<const v4i *>(
-            L + (C_::NFP + wi * IB + ib) * kFragBytes + lane * 16);
-      // The compiler starts each block with the MFMA of the longest
-      // accumulation chain (slice pair 1, S), so B' slice S is read second.
-      v4i pf[S];
-      pf[S - 1] = *reinterpret_cast<const v4i *>(L + ((S - 1) * WJ + wj) * kFragBytes + lane * 16);
+        for (int ib = 0; ib < IB; ++ib) qa[ib] = read_q(0, ib);
+        pf[S - 1] = *reinterpret_cast<const v4i *>(L + ((S - 1) * WJ + wj) * kFragBytes + lane * 16);
 #pragma unroll
-      for (int q = 0; q < S - 1; ++q)
-        pf[q] = *reinterpret_cast<const v4i *>(L + (q * WJ + wj) * kFragBytes + lane * 16);
+        for (int q = 0; q < S - 1; ++q)
+          pf[q] = *reinterpret_cast<const v4i *>(L + (q * WJ + wj) * kFragBytes + lane * 16);
 #pragma unroll
-      for (int p = 1; p < S; ++p)
+        for (int p = 0; p < S; ++p) {
+          if (p + 1 < S) {
 #pragma unroll
-        for (int ib = 0; ib < IB; ++ib)
-          qf[p][ib] = *reinterpret_cast<const v4i *>(
-              L + (C_::NFP + p * C_::NQB + wi * IB + ib) * kFragBytes + lane * 16);
-      // EARLY keeps the reads above the MFMAs (the scheduler would otherwise
-      // sink each A' read to just before its first use and expose its
-      // latency); for large S the registers of all fragments would not fit
-      if constexpr (EARLY && S * (1 + IB) <= 18) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int p = 0; p < S; ++p) {
-#pragma unroll
-        for (int ib = 0; ib < IB; ++ib) {
-#pragma unroll
-          for (int q = 0; q < S - p; ++q) {
-            if (XN > 0 && p >= PM)  // the second set of diagonal p + q
-              accx[ib][p + q - PM] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                  pf[q], qf[p][ib], accx[ib][p + q - PM], 0, 0, 0);
-            else
-              acc[ib][p + q] =
-                  __builtin_amdgcn_mfma_i32_32x32x32_i8(pf[q], qf[p][ib], acc[ib][p + q], 0, 0, 0);
+            for (int ib = 0; ib < IB; ++ib) qb[ib] = read_q(p + 1, ib);
           }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+            for (int q = 0; q < S - p; ++q) mfma(p, q, ib, pf[q], qa[ib]);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib) qa[ib] = qb[ib];
         }
+      } else {
+        // All fragment reads of the block are issued up front, A' of slice 1
+        // first; a wave's LDS reads return in order, so each MFMA waits only
+        // for the reads it needs and the later ones arrive under the earlier
+        // MFMAs.
+        v4i qf[S][IB];
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) qf[0][ib] = read_q(0, ib);
+        // The compiler starts each block with the MFMA of the longest
+        // accumulation chain (slice pair 1, S), so B' slice S is read second.
+        v4i pf[S];
+        pf[S - 1] = *reinterpret_cast<const v4i *>(L + ((S - 1) * WJ + wj) * kFragBytes + lane * 16);
+#pragma unroll
+        for (int q = 0; q < S - 1; ++q)
+          pf[q] = *reinterpret_cast<const v4i *>(L + (q * WJ + wj) * kFragBytes + lane * 16);
+#pragma unroll
+        for (int p = 1; p < S; ++p)
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib) qf[p][ib] = read_q(p, ib);
+        // EARLY keeps the reads above the MFMAs (the scheduler would otherwise
+        // sink each A' read to just before its first use and expose its
+        // latency); for large S the registers of all fragments would not fit
+        if constexpr (EARLY && S * (1 + IB) <= 18) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+          for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+            for (int q = 0; q < S - p; ++q) mfma(p, q, ib, pf[q], qf[p][ib]);
       }
       if constexpr (chunked) {
         if (kb + 1 == next_flush && kb + 1 < nkb) {
