@@ -166,11 +166,11 @@ __global__ void __launch_bounds__(64 * WJ * WI, 512 / (64 * WJ * WI)) k_ozgemm(G
         return *reinterpret_cast<const v4i *>(L + (C_::NFP + p * C_::NQB + wi * IB + ib) * kFragBytes +
                                               lane * 16);
       };
-      if constexpr (IB >= 2 && !EARLY) {
-        // Two A' blocks per wave: the fragments of every slice do not fit the
-        // registers next to the 2 S accumulator sets, and left to itself the
-        // compiler read each A' fragment into one register set just before
-        // its MFMAs, waiting out every LDS latency. Here the A' reads of slice
+      if constexpr (!EARLY) {
+        // Left to itself the compiler reads each A' fragment just before its
+        // MFMAs (with two A' blocks per wave, into one register set: the
+        // fragments of every slice do not fit next to the 2 S accumulator
+        // sets) and waits out every LDS latency. Here the A' reads of slice
         // p + 1 go out before the MFMAs of slice p (two register sets), the
         // order pinned by scheduling barriers.
         v4i pf[S], qa[IB], qb[IB];
