@@ -10,14 +10,17 @@ GPU path:
 
 L1 arithmetic: every complex product is (ar br - ai bi, ar bi + ai br) and
    every quotient a / b is ((ar br + ai bi) / d, (ai br - ar bi) / d) with
-   d = br br + bi bi, each real operation rounded on its own.
+   d = br br + bi bi, each real operation rounded on its own. The LU
+   multipliers are products with the pivot's reciprocal, l = a (1 / p) with
+   1 / p = (pr / d, (-pi) / d), as the reference LAPACK's unblocked
+   factorization scales a column by the reciprocal of its pivot.
 L2 pivoting: in column c the pivot is the first row of rows c..n-1 with the
    largest |Re| + |Im| (the measure of the reference LAPACK's izamax; a NaN
    counts as the largest, as numpy's argmax takes it); rows c and pivot are
    exchanged.
 L3 factorization (right-looking, panels of nb columns): per column of the
    panel, pivot and exchange within the panel columns, multipliers
-   l_i = a_ic / a_cc stored in place, a_ik -= l_i a_ck for the later panel
+   l_i = a_ic (1 / a_cc) stored in place, a_ik -= l_i a_ck for the later panel
    columns; then the panel's exchanges on all other columns; U12 = L11^-1 A12
    by forward substitution (x_r -= l_rk x_k for k = 0..r-1); then
    A22 <- update(A22, L21, U12), the GEMM model C - A B.
@@ -42,6 +45,12 @@ def _zdiv(ar, ai, br, bi):
     d = br * br + bi * bi
     with np.errstate(divide="ignore", invalid="ignore"):   # a zero pivot gives Inf/NaN, as on the GPU
         return (ar * br + ai * bi) / d, (ai * br - ar * bi) / d
+
+
+def _zrcp(br, bi):
+    d = br * br + bi * bi
+    with np.errstate(divide="ignore", invalid="ignore"):   # a zero pivot gives NaN, as on the GPU
+        return br / d, -bi / d
 
 
 def update_model(kind: str, slices: int):
@@ -96,7 +105,8 @@ def zgetrf(A, nb: int, update):
             singular = singular or not v.max() > 0
             ipiv[c] = piv
             _swap_rows(R, I, c, piv, panel)
-            lr, li = _zdiv(R[c + 1:, c], I[c + 1:, c], R[c, c], I[c, c])
+            rr, ri = _zrcp(R[c, c], I[c, c])
+            lr, li = _zmul(R[c + 1:, c], I[c + 1:, c], rr, ri)
             R[c + 1:, c], I[c + 1:, c] = lr, li
             for k in range(c + 1, j1):
                 pr, pi = _zmul(lr, li, R[c, k], I[c, k])

@@ -7,6 +7,9 @@
 // for bit:
 //   product   (ar br - ai bi, ar bi + ai br)
 //   quotient  d = br br + bi bi, ((ar br + ai bi) / d, (ai br - ar bi) / d)
+//   multiplier a_ic (1 / a_cc), the reciprocal (pr / d, (-pi) / d) with
+//             d = pr pr + pi pi (the reference LAPACK's unblocked
+//             factorization scales the column by the pivot's reciprocal too)
 //   pivot     the first row of the largest |Re| + |Im| in the column (NaN
 //             counts as the largest)
 #include "ozaki_internal.hpp"
@@ -32,6 +35,10 @@ __device__ __forceinline__ Z zdiv(Z a, Z b) {
   const double d = add_rn(mul_rn(b.re, b.re), mul_rn(b.im, b.im));
   return Z{__ddiv_rn(add_rn(mul_rn(a.re, b.re), mul_rn(a.im, b.im)), d),
            __ddiv_rn(sub_rn(mul_rn(a.im, b.re), mul_rn(a.re, b.im)), d)};
+}
+__device__ __forceinline__ Z zrcp(Z b) {
+  const double d = add_rn(mul_rn(b.re, b.re), mul_rn(b.im, b.im));
+  return Z{__ddiv_rn(b.re, d), __ddiv_rn(-b.im, d)};
 }
 __device__ __forceinline__ double cabs1(Z a) { return add_rn(fabs(a.re), fabs(a.im)); }
 
@@ -133,59 +140,70 @@ __global__ void __launch_bounds__(256) k_pivot_swap(double2 *A, int64_t lda, int
   }
 }
 
-// Panel update after the pivot of column c: a_ik -= (a_ic / a_cc) a_ck for
+// Panel update after the pivot of column c: a_ik -= (a_ic (1 / a_cc)) a_ck for
 // rows i > c and panel columns c < k < p1, one thread per element (each
 // computes its row's multiplier from the unscaled a_ic).
 __global__ void __launch_bounds__(256) k_panel_update(double2 *A, int64_t lda, int64_t n, int64_t c) {
   const int64_t i = c + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t k = c + 1 + blockIdx.y;
   if (i >= n) return;
-  const Z l = zdiv(ld(A + i + c * lda), ld(A + c + c * lda));
+  const Z l = zmul(ld(A + i + c * lda), zrcp(ld(A + c + c * lda)));
   st(A + i + k * lda, zsub(ld(A + i + k * lda), zmul(l, ld(A + c + k * lda))));
 }
 
-// End of the panel [p0, p1): the multipliers l_ic = a_ic / a_cc of every
+// End of the panel [p0, p1): the multipliers l_ic = a_ic (1 / a_cc) of every
 // panel column c, rows i > c, in place (one thread per entry).
 __global__ void __launch_bounds__(256) k_panel_scale(double2 *A, int64_t lda, int64_t n, int64_t p0) {
   const int64_t c = p0 + blockIdx.y;
   const int64_t i = p0 + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i <= c || i >= n) return;
-  st(A + i + c * lda, zdiv(ld(A + i + c * lda), ld(A + c + c * lda)));
+  st(A + i + c * lda, zmul(ld(A + i + c * lda), zrcp(ld(A + c + c * lda))));
+}
+
+// Pivot order of the leaf as one key per candidate: the bits of |Re| + |Im|
+// (a non-negative double, whose bit patterns order like its values) with
+// every NaN mapped to one key above +inf, and the row below the leaf's first
+// row as a 32-bit tie-break. The larger key wins, equal keys go to the lower
+// row: the order `beats` defines, in two integer compares.
+constexpr uint64_t kNaNKey = 0x7FF8000000000000ull;
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+__device__ __forceinline__ uint64_t pivot_key(double v) {
+  return v != v ? kNaNKey : (uint64_t)__double_as_longlong(v);
+}
+__device__ __forceinline__ bool key_beats(uint64_t k, uint32_t r, uint64_t bk, uint32_t br) {
+  return (k > bk) | ((k == bk) & (r < br));
 }
 
 // One step of a wave's pivot reduction with a DPP lane pattern (VALU moves, no
 // LDS round trip): each lane compares with the lane CTRL names.
 template <int CTRL>
-__device__ __forceinline__ void best_dpp(double &best, int64_t &bi) {
-  const int64_t vb = __double_as_longlong(best);
-  const int vlo = (int)vb, vhi = (int)(vb >> 32), ilo = (int)bi, ihi = (int)(bi >> 32);
-  const int ovlo = __builtin_amdgcn_update_dpp(vlo, vlo, CTRL, 0xF, 0xF, false);
-  const int ovhi = __builtin_amdgcn_update_dpp(vhi, vhi, CTRL, 0xF, 0xF, false);
-  const int oilo = __builtin_amdgcn_update_dpp(ilo, ilo, CTRL, 0xF, 0xF, false);
-  const int oihi = __builtin_amdgcn_update_dpp(ihi, ihi, CTRL, 0xF, 0xF, false);
-  const double ov = __longlong_as_double((int64_t)(((uint64_t)(uint32_t)ovhi << 32) | (uint32_t)ovlo));
-  const int64_t oi = (int64_t)(((uint64_t)(uint32_t)oihi << 32) | (uint32_t)oilo);
-  const bool take = beats(ov, oi, best, bi);
-  best = take ? ov : best;
-  bi = take ? oi : bi;
+__device__ __forceinline__ void best_dpp(uint64_t &bk, uint32_t &br) {
+  const int klo = (int)(uint32_t)bk, khi = (int)(uint32_t)(bk >> 32), r = (int)br;
+  const uint32_t oklo = (uint32_t)__builtin_amdgcn_update_dpp(klo, klo, CTRL, 0xF, 0xF, false);
+  const uint32_t okhi = (uint32_t)__builtin_amdgcn_update_dpp(khi, khi, CTRL, 0xF, 0xF, false);
+  const uint32_t orow = (uint32_t)__builtin_amdgcn_update_dpp(r, r, CTRL, 0xF, 0xF, false);
+  const uint64_t ok = ((uint64_t)okhi << 32) | oklo;
+  const bool take = key_beats(ok, orow, bk, br);
+  bk = take ? ok : bk;
+  br = take ? orow : br;
 }
 
-// The wave's best (value, row) in every lane: within each 16-lane row by DPP
+// The wave's best (key, row) in every lane: within each 16-lane row by DPP
 // (quad exchanges 1 and 2, then half-row and row mirrors), across rows by two
-// shuffles. The order of comparisons does not matter: `beats` is a strict
-// total order on (value, row) pairs.
-__device__ __forceinline__ void wave_best(double &best, int64_t &bi) {
-  best_dpp<0xB1>(best, bi);   // quad_perm [1, 0, 3, 2]
-  best_dpp<0x4E>(best, bi);   // quad_perm [2, 3, 0, 1]
-  best_dpp<0x141>(best, bi);  // row_half_mirror
-  best_dpp<0x140>(best, bi);  // row_mirror
+// shuffles. The order of comparisons does not matter: the (key, row) order is
+// a strict total order.
+__device__ __forceinline__ void wave_best(uint64_t &bk, uint32_t &br) {
+  best_dpp<0xB1>(bk, br);   // quad_perm [1, 0, 3, 2]
+  best_dpp<0x4E>(bk, br);   // quad_perm [2, 3, 0, 1]
+  best_dpp<0x141>(bk, br);  // row_half_mirror
+  best_dpp<0x140>(bk, br);  // row_mirror
 #pragma unroll
   for (int o = 16; o < 64; o <<= 1) {
-    const double ov = __shfl_xor(best, o);
-    const int64_t oi = __shfl_xor(bi, o);
-    const bool take = beats(ov, oi, best, bi);
-    best = take ? ov : best;
-    bi = take ? oi : bi;
+    const uint64_t ok = __shfl_xor(bk, o);
+    const uint32_t orow = (uint32_t)__shfl_xor((int)br, o);
+    const bool take = key_beats(ok, orow, bk, br);
+    bk = take ? ok : bk;
+    br = take ? orow : br;
   }
 }
 
@@ -199,9 +217,10 @@ __device__ __forceinline__ void wave_best(double &best, int64_t &bi) {
 //     the 8 wave results itself and reads the pivot row from its wave's slot;
 //   interchange of rows c and the pivot row within the leaf columns;
 //   update a_ik -= l_ic a_ck of rows i > c, leaf columns k > c, with the
-//     multiplier l_ic = a_ic / a_cc, which replaces a_ic.
+//     multiplier l_ic = a_ic (1 / a_cc), which replaces a_ic (every thread
+//     forms the reciprocal itself).
 // These are k_pivot_swap's, k_panel_update's and k_panel_scale's operations on
-// the leaf columns (the multiplier is the same quotient whether taken at step
+// the leaf columns (the multiplier is the same product whether taken at step
 // c or at the end of the panel: column c is only permuted after step c), so
 // the leaf ends bit for bit as it would under them; the other panel columns
 // take the leaf's interchanges and updates in k_lu_trail. A
@@ -209,6 +228,8 @@ __device__ __forceinline__ void wave_best(double &best, int64_t &bi) {
 // the others (straight-line code, no per-column tests) but never read by a
 // pivot search and never stored. The LDS slots alternate between even and odd
 // steps, so a thread one step ahead never overwrites a slot still being read.
+// RPT is 4, 8 or 16 for leaves of 8, 4 or 2 columns (up to 2048, 4096 or 8192
+// rows); a leaf of 8 columns over at most 1024 or 512 rows takes RPT 2 or 1.
 constexpr int kLeafThreads = 512;
 
 template <int RPT, int L>
@@ -218,16 +239,19 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
   constexpr int NT = kLeafThreads, NW = NT / 64;
   __shared__ double2 srow[2][NW][L];
   __shared__ double2 sc[2][L];
-  __shared__ double sv[2][NW];
-  __shared__ int64_t si[2][NW];
+  __shared__ uint64_t sk[2][NW];
+  __shared__ uint32_t sr[2][NW];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int w = (int)(c1 - c0);
+  // rows below the leaf's first row (the launch guarantees rows <= NT * RPT)
+  const uint32_t rows = (uint32_t)(n - c0);
   Z x[RPT][L];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int64_t i = c0 + t + (int64_t)NT * j;
+    const uint32_t r = (uint32_t)(t + NT * j);
 #pragma unroll
-    for (int k = 0; k < L; ++k) x[j][k] = (i < n && k < w) ? ld(A + i + (c0 + k) * lda) : Z{0.0, 0.0};
+    for (int k = 0; k < L; ++k)
+      x[j][k] = (r < rows && k < w) ? ld(A + c0 + r + (c0 + k) * lda) : Z{0.0, 0.0};
   }
   int64_t pivs[L];
   int first_zero = -1;
@@ -235,19 +259,19 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
   for (int cc = 0; cc < L; ++cc) {
     if (cc >= w) break;
     const int b = cc & 1;
-    const int64_t c = c0 + cc;
-    double best = -1.0;
-    int64_t bi = n;
+    uint64_t bk = 0;
+    uint32_t br = kNoRow;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {  // a thread's rows in increasing order
-      const int64_t i = c0 + t + (int64_t)NT * j;
-      const bool take = i >= c && i < n && beats(cabs1(x[j][cc]), i, best, bi);
-      best = take ? cabs1(x[j][cc]) : best;
-      bi = take ? i : bi;
+      const uint32_t r = (uint32_t)(t + NT * j);
+      const uint64_t k = pivot_key(cabs1(x[j][cc]));
+      const bool take = (r >= (uint32_t)cc) & (r < rows) & key_beats(k, r, bk, br);
+      bk = take ? k : bk;
+      br = take ? r : br;
     }
-    wave_best(best, bi);
-    if (bi < n && ((bi - c0) & (NT - 1)) == t) {
-      const int jb = (int)((bi - c0) / NT);
+    wave_best(bk, br);
+    if (br != kNoRow && (int)(br & (NT - 1)) == t) {
+      const int jb = (int)(br / NT);
 #pragma unroll
       for (int j = 0; j < RPT; ++j)
         if (j == jb)
@@ -255,47 +279,48 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
           for (int k = 0; k < L; ++k) srow[b][wave][k] = make_double2(x[j][k].re, x[j][k].im);
     }
     if (lane == 0) {
-      sv[b][wave] = best;
-      si[b][wave] = bi;
+      sk[b][wave] = bk;
+      sr[b][wave] = br;
     }
     if (t == cc)  // row c = c0 + cc is thread cc's first row
 #pragma unroll
       for (int k = 0; k < L; ++k) sc[b][k] = make_double2(x[0][k].re, x[0][k].im);
     __syncthreads();
-    double cv[NW];
-    int64_t ci[NW];
+    uint64_t ck[NW];
+    uint32_t cr[NW];
 #pragma unroll
     for (int v = 0; v < NW; ++v) {  // all reads first, then the reduction
-      cv[v] = sv[b][v];
-      ci[v] = si[b][v];
+      ck[v] = sk[b][v];
+      cr[v] = sr[b][v];
     }
-    best = cv[0];
-    bi = ci[0];
+    bk = ck[0];
+    br = cr[0];
     int win = 0;
 #pragma unroll
     for (int v = 1; v < NW; ++v) {
-      const bool take = beats(cv[v], ci[v], best, bi);
-      best = take ? cv[v] : best;
-      bi = take ? ci[v] : bi;
+      const bool take = key_beats(ck[v], cr[v], bk, br);
+      bk = take ? ck[v] : bk;
+      br = take ? cr[v] : br;
       win = take ? v : win;
     }
     // row c takes part, so the pivot is a row of [c, n); the pivots go out
-    // after the last step (a store in flight would hold up the next barrier)
-    const int64_t piv = bi;
+    // after the last step (a store in flight would hold up the next barrier).
+    // A pivot of |Re| + |Im| = 0 or NaN makes the matrix singular.
+    const int64_t piv = c0 + br;
     pivs[cc] = piv;
-    if (!(best > 0.0) && first_zero < 0) first_zero = cc;
+    if ((bk == 0 || bk == kNaNKey) && first_zero < 0) first_zero = cc;
     Z pr[L];  // the pivot row: row c after the interchange
 #pragma unroll
     for (int k = 0; k < L; ++k) {
       const double2 v = srow[b][win][k];
       pr[k] = Z{v.x, v.y};
     }
-    if (piv != c) {
+    if (br != (uint32_t)cc) {
       if (t == cc)
 #pragma unroll
         for (int k = 0; k < L; ++k) x[0][k] = pr[k];
-      if (((piv - c0) & (NT - 1)) == t) {
-        const int jp = (int)((piv - c0) / NT);
+      if ((int)(br & (NT - 1)) == t) {
+        const int jp = (int)(br / NT);
 #pragma unroll
         for (int j = 0; j < RPT; ++j)
           if (j == jp)
@@ -306,11 +331,12 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
             }
       }
     }
+    const Z rc = zrcp(pr[cc]);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const int64_t i = c0 + t + (int64_t)NT * j;
-      if (i > c && i < n) {
-        const Z l = zdiv(x[j][cc], pr[cc]);
+      const uint32_t r = (uint32_t)(t + NT * j);
+      if (r > (uint32_t)cc && r < rows) {
+        const Z l = zmul(x[j][cc], rc);
         x[j][cc] = l;  // the multiplier, final up to later interchanges
 #pragma unroll
         for (int k = cc + 1; k < L; ++k) x[j][k] = zsub(x[j][k], zmul(l, pr[k]));
@@ -319,11 +345,11 @@ __global__ void __launch_bounds__(kLeafThreads) k_lu_leaf(double2 *A, int64_t ld
   }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int64_t i = c0 + t + (int64_t)NT * j;
-    if (i < n)
+    const uint32_t r = (uint32_t)(t + NT * j);
+    if (r < rows)
 #pragma unroll
       for (int k = 0; k < L; ++k)
-        if (k < w) st(A + i + (c0 + k) * lda, x[j][k]);
+        if (k < w) st(A + c0 + r + (c0 + k) * lda, x[j][k]);
   }
   if (t == 0) {
 #pragma unroll
@@ -723,7 +749,14 @@ hipError_t launch_lu_panel(double2 *A, int64_t lda, int64_t n, int64_t p0, int64
     const int64_t c1 = std::min(p1, c0 + L);
     const dim3 lb(kLeafThreads);
     switch (L) {
-      case 8: hipLaunchKernelGGL((k_lu_leaf<4, 8>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
+      case 8:
+        if (n - c0 <= kLeafThreads)
+          hipLaunchKernelGGL((k_lu_leaf<1, 8>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular);
+        else if (n - c0 <= 2 * kLeafThreads)
+          hipLaunchKernelGGL((k_lu_leaf<2, 8>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular);
+        else
+          hipLaunchKernelGGL((k_lu_leaf<4, 8>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular);
+        break;
       case 4: hipLaunchKernelGGL((k_lu_leaf<8, 4>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
       default: hipLaunchKernelGGL((k_lu_leaf<16, 2>), dim3(1), lb, 0, st, A, lda, n, c0, c1, ipiv, singular); break;
     }
