@@ -48,7 +48,7 @@ def _matrix(n, seed):
 
 
 @pytest.mark.parametrize("kind,s,n,nb", [("b8", 6, 200, 64), ("t7", 5, 200, 64), ("b8", 4, 130, 32),
-                                         ("t7", 7, 96, 96)])
+                                         ("t7", 7, 96, 96), ("b8", 6, 300, 128), ("t7", 6, 250, 100)])
 def test_lu_and_inverse_bit_exact(kind, s, n, nb):
     A = _matrix(n, 1600 + n + s)
     assert oz.ozaki_set_split(kind) == 0
