@@ -27,6 +27,12 @@ from . import (MLP_PARAMS, OzakiError, ozaki_features, ozaki_mlp_adam, ozaki_mlp
 S_LO = 3
 S_HI = 12
 KAPPA = 8.0      # probe safety factor used when the weights file stores none
+# What a weights file was trained on: the library's feature vector and network.
+# A file stores it as `feature_spec`; load() refuses a file without it or with
+# another one (weights trained on other features would be read as if they fit).
+FEATURE_SPEC = ("ozaki-selector/1: features = op(A) row exponent offsets, bins 0..30 + zero "
+                "(32); op(B) column offsets, bins 0..29 + zero (31); log2(k)/16; "
+                f"network 64-128-128-1 ReLU, BF16 products, {MLP_PARAMS} FP32 parameters")
 
 
 def pair_sizes(rng, count, mn_choices=(32, 64), kmax_j=32, mn_law=False):
@@ -402,18 +408,26 @@ def calibrate_auto(pred, errs, est, work, target, log=None):
 
 
 def save(path, theta, margin, target, meta):
+    meta = {k: v for k, v in meta.items() if k != "feature_spec"}
     np.savez(path, theta=np.asarray(theta, dtype=np.float32), margin=np.float32(margin),
-             target=np.float64(target), **{k: np.asarray(v) for k, v in meta.items()})
+             target=np.float64(target), feature_spec=np.asarray(FEATURE_SPEC),
+             **{k: np.asarray(v) for k, v in meta.items()})
 
 
 def load(path, with_meta=False):
     """(theta, margin, target) of a saved selector, plus the dict of its other
     stored values when with_meta is set."""
     z = np.load(path, allow_pickle=False)
+    spec = str(z["feature_spec"]) if "feature_spec" in z.files else None
+    if spec != FEATURE_SPEC:
+        raise ValueError(f"{path}: selector weights for features {spec!r}, the library computes "
+                         f"{FEATURE_SPEC!r}")
+    if z["theta"].size != MLP_PARAMS:
+        raise ValueError(f"{path}: {z['theta'].size} parameters, the network has {MLP_PARAMS}")
     out = (z["theta"], float(z["margin"]), float(z["target"]))
     if with_meta:
         meta = {key: (z[key].item() if z[key].ndim == 0 else z[key]) for key in z.files
-                if key not in ("theta", "margin", "target")}
+                if key not in ("theta", "margin", "target", "feature_spec")}
         return out + (meta,)
     return out
 
