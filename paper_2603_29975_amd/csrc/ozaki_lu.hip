@@ -387,67 +387,69 @@ __global__ void __launch_bounds__(kTrailThreads) k_lu_trail(double2 *A, int64_t 
   const bool left = b < c0 - p0;
   const int64_t k = left ? p0 + b : c1 + (b - (c0 - p0));
   double2 *col = A + k * lda;
-  // every thread reads the w pivots (an entry outside [c, n) is no exchange)
-  int64_t pv[L];
-#pragma unroll
-  for (int q = 0; q < L; ++q) {
-    const int64_t p = q < w ? ipiv[c0 + q] : c0 + q;
-    pv[q] = (p < c0 + q || p >= n) ? c0 + q : p;
-  }
-  if (!left && t < w * w) {
-    const int r = t % w, q = t / w;
-    if (r > q) lm[r][q] = A[c0 + r + (c0 + q) * lda];
-  }
-  // slot of each exchange's pivot row: p - c0 inside the leaf, else w + the
-  // number of distinct pivot rows below c1 named before it first is
-  int ps[L];
-  int m = w;
-#pragma unroll
-  for (int q = 0; q < L; ++q) {
-    int s = q;
-    if (q < w) {
-      if (pv[q] < c1) {
-        s = (int)(pv[q] - c0);
-      } else {
-        int first = q, rank = 0;
-#pragma unroll
-        for (int e = 0; e < L; ++e)
-          if (e < q && pv[e] == pv[q] && e < first) first = e;
-#pragma unroll
-        for (int e = 0; e < L; ++e) {
-          bool newrow = e < first && pv[e] >= c1;
-#pragma unroll
-          for (int f = 0; f < L; ++f)
-            if (f < e && pv[f] == pv[e]) newrow = false;
-          rank += newrow ? 1 : 0;
-        }
-        s = w + rank;
-        if (first == q) ++m;
-      }
-    }
-    ps[q] = s;
-  }
-  // thread t < m: the row of slot t and the slot whose entry ends there
+  // The interchanges touch at most 2 w <= 16 slots, so wave 0 alone works
+  // out the slots and gathers (the slot logic is uniform scalar code: the
+  // other waves would only queue on the CU's scalar unit behind it).
+  int m = 0;
   Z val{0.0, 0.0};
   int64_t row = 0;
-  if (t < m) {
-    if (t < w) {
-      row = c0 + t;
-    } else {
+  if (t < 64) {
+    // the w pivots (an entry outside [c, n) is no exchange)
+    int64_t pv[L];
 #pragma unroll
-      for (int q = 0; q < L; ++q)
-        if (q < w && ps[q] == t) row = pv[q];
+    for (int q = 0; q < L; ++q) {
+      const int64_t p = q < w ? ipiv[c0 + q] : c0 + q;
+      pv[q] = (p < c0 + q || p >= n) ? c0 + q : p;
     }
-    int src = t;
+    if (!left && t < w * w) {
+      const int r = t % w, q = t / w;
+      if (r > q) lm[r][q] = A[c0 + r + (c0 + q) * lda];
+    }
+    // slot of each exchange's pivot row: p - c0 inside the leaf, else w + the
+    // number of distinct pivot rows below c1 named before it first is. nw[e]:
+    // exchange e names a row below c1 that no earlier exchange named (O(L^2)
+    // compares in straight-line code).
+    bool nw[L];
+    m = w;
 #pragma unroll
-    for (int q = L - 1; q >= 0; --q)
-      if (q < w) src = src == q ? ps[q] : (src == ps[q] ? q : src);
-    int64_t srow = c0 + src;
-    if (src >= w)
+    for (int e = 0; e < L; ++e) {
+      bool fresh = e < w && pv[e] >= c1;
 #pragma unroll
-      for (int q = 0; q < L; ++q)
-        if (q < w && ps[q] == src) srow = pv[q];
-    val = ld(col + srow);
+      for (int f = 0; f < e; ++f) fresh = fresh && pv[f] != pv[e];
+      nw[e] = fresh;
+      m += fresh ? 1 : 0;
+    }
+    int ps[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      int first = q;  // the first exchange naming pv[q]
+#pragma unroll
+      for (int e = q - 1; e >= 0; --e) first = pv[e] == pv[q] ? e : first;
+      int rank = 0;
+#pragma unroll
+      for (int e = 0; e < q; ++e) rank += (nw[e] && e < first) ? 1 : 0;
+      ps[q] = q < w ? (pv[q] < c1 ? (int)(pv[q] - c0) : w + rank) : q;
+    }
+    // thread t < m: the row of slot t and the slot whose entry ends there
+    if (t < m) {
+      if (t < w) {
+        row = c0 + t;
+      } else {
+#pragma unroll
+        for (int q = 0; q < L; ++q)
+          if (q < w && ps[q] == t) row = pv[q];
+      }
+      int src = t;
+#pragma unroll
+      for (int q = L - 1; q >= 0; --q)
+        if (q < w) src = src == q ? ps[q] : (src == ps[q] ? q : src);
+      int64_t srow = c0 + src;
+      if (src >= w)
+#pragma unroll
+        for (int q = 0; q < L; ++q)
+          if (q < w && ps[q] == src) srow = pv[q];
+      val = ld(col + srow);
+    }
   }
   __syncthreads();  // every slot read before any is overwritten
   if (left) {
