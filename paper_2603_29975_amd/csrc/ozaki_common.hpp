@@ -29,20 +29,17 @@ inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 // Code of one FP64 value: 0 for +-0, kCodeBad for Inf/NaN, otherwise
 // e + kCodeBias where e is the frexp exponent (|v| in [2^(e-1), 2^e)).
 // The frexp exponent of a row maximum is the maximum of the entries' codes.
+// Written with selects, not branches: a scan issues its loads back to back
+// only when nothing between them depends on a loaded value.
 __device__ __forceinline__ int expo_code(double v) {
   const uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
   const uint32_t E = (uint32_t)(b >> 52);
-  if (E == 0x7ffu) return kCodeBad;
-  if (b == 0) return 0;
-  int e;
-  if (E == 0) {
-    // subnormal: value = b * 2^-1074 with its top set bit at position h
-    const int h = 63 - __clzll((long long)b);
-    e = h - 1073;
-  } else {
-    e = (int)E - 1022;
-  }
-  return e + kCodeBias;
+  // subnormal: value = b * 2^-1074 with its top set bit at position h (b | 1
+  // keeps the count defined for b = 0, whose code is 0 anyway)
+  const int h = 63 - __clzll((long long)(b | 1));
+  const int e = E == 0 ? h - 1073 : (int)E - 1022;
+  const int c = b == 0 ? 0 : e + kCodeBias;
+  return E == 0x7ffu ? kCodeBad : c;
 }
 
 __host__ __device__ __forceinline__ bool code_bad(int c) { return c >= kCodeBad; }

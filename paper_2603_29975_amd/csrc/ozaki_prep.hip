@@ -50,8 +50,15 @@ __device__ __forceinline__ void scan_rowsfast_block(const View &v, int64_t rb, i
   const int64_t r = rb * 64 + (tid & 63);
   int c = 0;
   if (r < v.R) {
-    // four loads in flight per pass, then the remainder
+    // eight loads in flight per pass (a block that covers a long contraction
+    // alone is latency-bound), then four, then the remainder
     int64_t l = l0 + (tid >> 6);
+    for (; l + 28 < l1; l += 32) {
+      int a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = elem_code<CPLX>(v.base, r + (l + 4 * q) * v.sl);
+      c = max(c, max(max(max(a[0], a[1]), max(a[2], a[3])), max(max(a[4], a[5]), max(a[6], a[7]))));
+    }
     for (; l + 12 < l1; l += 16) {
       const int a0 = elem_code<CPLX>(v.base, r + l * v.sl);
       const int a1 = elem_code<CPLX>(v.base, r + (l + 4) * v.sl);
